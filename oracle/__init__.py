@@ -1,0 +1,188 @@
+"""FP64 CPU oracle for the circle-packing penalty-energy descent.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the independent checker of the HIP
+library: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg
+of ``bench.py`` may import it.  It shares no code with the GPU path.
+
+The arithmetic lives in ``pecc_oracle.c`` (plain C, FP64, brute force over all
+pairs, built with ``-O2 -ffp-contract=off``); this module only marshals numpy
+arrays through ctypes.  Each function names the part of the paper it follows:
+
+  energy_grad        Def. 3.1 / Def. 3.2 (Eq. 3, Eq. 5) and their gradient
+  batch_energy_grad  Eq. 7 (batch energy of Sec. 4.1)
+  neighbors          Gamma(i) of Sec. 4.3, FP64 predicate on FP32 inputs
+  two_loop           H g for the inverse update of Eq. 10-11 (limited memory)
+  descend            Alg. 1 with one batch, L-BFGS reading of Eq. 8-11
+  verify             Eq. 1-2 checked through E (Eq. 5) in FP64
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pecc_oracle.c")
+_LIB = os.path.join(_HERE, "_pecc_oracle.so")
+
+STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED",
+          4: "STALLED", 5: "MAX_ITER", 6: "NONFINITE"}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c99", "-Wall", "-shared", "-fPIC",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp, fp, ip = C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32)
+        L.oracle_energy_grad.restype = C.c_double
+        L.oracle_energy_grad.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp, dp, dp]
+        L.oracle_batch_energy_grad.restype = C.c_double
+        L.oracle_batch_energy_grad.argtypes = [C.c_int, dp, C.c_double, C.c_double, ip, dp]
+        L.oracle_neighbors.restype = C.c_int64
+        L.oracle_neighbors.argtypes = [C.c_int, fp, C.c_double, ip, ip, C.c_int64]
+        L.oracle_two_loop.restype = None
+        L.oracle_two_loop.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp]
+        L.oracle_descend.restype = C.c_int
+        L.oracle_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_void_p, dp]
+        L.oracle_verify.restype = C.c_int
+        L.oracle_verify.argtypes = [C.c_int, fp, C.c_double, C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def energy_grad(xy, R: float, rad: float = 1.0):
+    """E, E_pair, E_cont and dE/dx (shape (n, 2)) at FP64 positions xy (n, 2)."""
+    xy, p = _d(np.asarray(xy).reshape(-1, 2))
+    n = xy.shape[0]
+    g = np.zeros((n, 2), dtype=np.float64)
+    ep, ec = C.c_double(), C.c_double()
+    E = lib().oracle_energy_grad(n, p, float(R), float(rad), C.byref(ep), C.byref(ec),
+                                 g.ctypes.data_as(C.POINTER(C.c_double)))
+    return E, ep.value, ec.value, g
+
+
+def energy(xy, R: float, rad: float = 1.0) -> float:
+    xy, p = _d(np.asarray(xy).reshape(-1, 2))
+    return lib().oracle_energy_grad(xy.shape[0], p, float(R), float(rad), None, None, None)
+
+
+def batch_energy_grad(xy, R: float, mask, rad: float = 1.0):
+    """Eq. 7 batch energy of the circles with mask != 0 and its gradient."""
+    xy, p = _d(np.asarray(xy).reshape(-1, 2))
+    m = np.ascontiguousarray(mask, dtype=np.int32)
+    g = np.zeros_like(xy)
+    E = lib().oracle_batch_energy_grad(xy.shape[0], p, float(R), float(rad),
+                                       m.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       g.ctypes.data_as(C.POINTER(C.c_double)))
+    return E, g
+
+
+def neighbors(xy32, cutoff: float = 2.3):
+    """Half pair set {(i, j): i < j, l_ij < cutoff} (FP64 test on FP32 input),
+    ordered by i then j; returns int32 arrays (pi, pj)."""
+    xy, p = _f(np.asarray(xy32, dtype=np.float32).reshape(-1, 2))
+    n = xy.shape[0]
+    L = lib()
+    cnt = L.oracle_neighbors(n, p, float(cutoff), None, None, 0)
+    pi = np.zeros(max(cnt, 1), dtype=np.int32)
+    pj = np.zeros(max(cnt, 1), dtype=np.int32)
+    L.oracle_neighbors(n, p, float(cutoff), pi.ctypes.data_as(C.POINTER(C.c_int32)),
+                       pj.ctypes.data_as(C.POINTER(C.c_int32)), cnt)
+    return pi[:cnt], pj[:cnt]
+
+
+def two_loop(S, Y, g):
+    """r = H g for the stored pairs S, Y (k rows, oldest first)."""
+    S, ps = _d(np.atleast_2d(S))
+    Y, py = _d(np.atleast_2d(Y))
+    g, pg = _d(np.asarray(g).reshape(-1))
+    k = S.shape[0] if S.size else 0
+    r = np.zeros_like(g)
+    lib().oracle_two_loop(g.shape[0], k, ps, py, pg, r.ctypes.data_as(C.POINTER(C.c_double)))
+    return r
+
+
+class _Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("max_iter", C.c_int32), ("max_halvings", C.c_int32),
+                ("ftol_window", C.c_int32), ("c1", C.c_double), ("eps_curv", C.c_double),
+                ("e_feasible", C.c_double), ("g_tol", C.c_double), ("ftol", C.c_double),
+                ("rad", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("evals", C.c_int32),
+                ("resets", C.c_int32), ("E", C.c_double), ("gnorm", C.c_double)]
+
+
+@dataclass
+class DescentParams:
+    """Descent constants.  Defaults: memory m = 10, the paper's MaxIter = 5000
+    and gradient stop 1e-12 (Sec. 6.1, Alg. 1), feasibility E < 1e-20."""
+    m: int = 10
+    max_iter: int = 5000
+    max_halvings: int = 40
+    ftol_window: int = 20
+    c1: float = 1e-4
+    eps_curv: float = 1e-8
+    e_feasible: float = 1e-20
+    g_tol: float = 1e-12
+    ftol: float = 0.0
+    rad: float = 1.0
+
+
+def descend(xy, R: float, params: DescentParams | None = None, trace: bool = False):
+    """Whole-instance L-BFGS descent in FP64.  Returns (xy_final, result, trace)."""
+    P = params or DescentParams()
+    x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
+    cp = _Params(**asdict(P))
+    cr = _Result()
+    tr = np.zeros(P.max_iter + 1, dtype=np.float64) if trace else None
+    rc = lib().oracle_descend(x.shape[0], px, float(R), C.byref(cp), C.byref(cr),
+                              tr.ctypes.data_as(C.POINTER(C.c_double)) if trace else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle_descend failed ({rc})")
+    res = {"status": STATUS[cr.status], "iters": cr.iters, "evals": cr.evals,
+           "resets": cr.resets, "E": cr.E, "gnorm": cr.gnorm}
+    if trace:
+        tr = tr[:cr.iters + 1]
+    return x, res, tr
+
+
+def verify(xy32, R: float, tol: float = 1e-20):
+    """FP64 feasibility of FP32 positions: E, max pair overlap, max container
+    overlap, feasible flag."""
+    xy, p = _f(np.asarray(xy32, dtype=np.float32).reshape(-1, 2))
+    out = np.zeros(3, dtype=np.float64)
+    f = lib().oracle_verify(xy.shape[0], p, float(R), float(tol),
+                            out.ctypes.data_as(C.POINTER(C.c_double)))
+    return {"E": out[0], "max_pair_overlap": out[1], "max_cont_overlap": out[2],
+            "feasible": bool(f)}

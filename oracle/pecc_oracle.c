@@ -1,0 +1,407 @@
+/*
+ * pecc_oracle.c -- plain FP64 CPU oracle for the penalty-energy descent of
+ * Zhou, He, Zheng & Li, "Geometric Batch Optimization for the Packing Equal
+ * Circles in a Circle Problem on Large Scale" (arXiv 2303.02650).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent checker of the HIP
+ * library.  Only the test suite, the smoke entry point and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the GPU path and includes nothing from it.
+ *
+ * Everything is brute force and FP64: every pair i<j is enumerated, no cell
+ * grid, no neighbor list, no blocking.  Build with -O2 -ffp-contract=off so
+ * that no multiply-add is fused (the neighbor predicate must round exactly
+ * like the GPU's, see oracle_neighbors).
+ *
+ * Sections of the paper followed:
+ *   Sec. 3.1, Eq. 1-2   problem (feasibility)
+ *   Def. 3.1 (Eq. 3)    overlap distances d_ij, d_i0
+ *   Def. 3.2 (Eq. 5)    elastic energy E = sum_{i<j} d_ij^2 + sum_i d_i0^2
+ *   Sec. 4.1, Eq. 7     batch energy E(x_p)
+ *   Sec. 4.1, Eq. 8-11  quasi-Newton step, BFGS inverse update
+ *   Sec. 4.1, Alg. 1    batch descent loop and its stop rule
+ *   Sec. 4.3            neighbor set Gamma(i) = { j != i : l_ij < l_cut }
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Energy and gradient: Def. 3.1 and Def. 3.2, written out pair by pair.     */
+/*                                                                           */
+/* rad is the circle radius (1 for the paper's unit circles; a value         */
+/* 1+mu describes circles inflated by a contact margin mu).  Overlap of i,j  */
+/* is d = max(0, 2 rad - l), container overlap d0 = max(0, rho + rad - R).   */
+/* d(d^2)/dc_i = 2 d * (-(c_i - c_j)/l); at l = 0 the pair adds (2rad)^2 to  */
+/* E and nothing to g (0 lies in the generalized gradient there).            */
+/* Returns E; e_pair / e_cont (nullable) get the two sums; grad (nullable,   */
+/* length 2n, interleaved like x) receives dE/dx.                            */
+/* ------------------------------------------------------------------------ */
+double oracle_energy_grad(int n, const double *xy, double R, double rad,
+                          double *e_pair, double *e_cont, double *grad)
+{
+    double sp = 0.0, sc = 0.0;
+    const double two_r = 2.0 * rad;
+    if (grad) memset(grad, 0, sizeof(double) * 2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const double xi = xy[2 * i], yi = xy[2 * i + 1];
+        for (int j = i + 1; j < n; ++j) {
+            const double dx = xi - xy[2 * j];
+            const double dy = yi - xy[2 * j + 1];
+            const double l2 = dx * dx + dy * dy;
+            if (l2 < two_r * two_r) {
+                const double l = sqrt(l2);
+                const double d = two_r - l;
+                sp += d * d;
+                if (grad && l > 0.0) {
+                    const double k = -2.0 * d / l;
+                    grad[2 * i] += k * dx;
+                    grad[2 * i + 1] += k * dy;
+                    grad[2 * j] -= k * dx;
+                    grad[2 * j + 1] -= k * dy;
+                }
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        const double x = xy[2 * i], y = xy[2 * i + 1];
+        const double rho = sqrt(x * x + y * y);
+        const double d0 = rho + rad - R;
+        if (d0 > 0.0) {
+            sc += d0 * d0;
+            if (grad && rho > 0.0) {
+                grad[2 * i] += 2.0 * d0 * x / rho;
+                grad[2 * i + 1] += 2.0 * d0 * y / rho;
+            }
+        }
+    }
+    if (e_pair) *e_pair = sp;
+    if (e_cont) *e_cont = sc;
+    return sp + sc;
+}
+
+/* Batch energy of Eq. 7: circles i with mask[i] != 0 form B_p.
+ *   E(x_p) = sum_{i in B_p} sum_{j != i} d_ij^2 [j not in B_p or j < i]
+ *          + sum_{i in B_p} d_i0^2
+ * grad (nullable, 2n) receives dE(x_p)/dx restricted to B_p (zero outside). */
+double oracle_batch_energy_grad(int n, const double *xy, double R, double rad,
+                                const int32_t *mask, double *grad)
+{
+    double e = 0.0;
+    const double two_r = 2.0 * rad;
+    if (grad) memset(grad, 0, sizeof(double) * 2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        if (!mask[i]) continue;
+        const double xi = xy[2 * i], yi = xy[2 * i + 1];
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = xi - xy[2 * j];
+            const double dy = yi - xy[2 * j + 1];
+            const double l2 = dx * dx + dy * dy;
+            if (!(l2 < two_r * two_r)) continue;
+            const double l = sqrt(l2);
+            const double d = two_r - l;
+            if (!mask[j] || j < i) e += d * d;
+            if (grad && l > 0.0) {
+                /* only the derivative with respect to c_i is kept: pairs
+                 * inside B_p are visited from both ends, pairs leaving B_p
+                 * once, and both give exactly dE/dc_i. */
+                const double k = -2.0 * d / l;
+                grad[2 * i] += k * dx;
+                grad[2 * i + 1] += k * dy;
+            }
+        }
+        const double rho = sqrt(xi * xi + yi * yi);
+        const double d0 = rho + rad - R;
+        if (d0 > 0.0) {
+            e += d0 * d0;
+            if (grad && rho > 0.0) {
+                grad[2 * i] += 2.0 * d0 * xi / rho;
+                grad[2 * i + 1] += 2.0 * d0 * yi / rho;
+            }
+        }
+    }
+    return e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbor set Gamma(i) of Sec. 4.3 with l_cut = cutoff, as the half set of */
+/* pairs i < j.  The predicate is evaluated in FP64 on FP32 coordinates:     */
+/*   dx = (double)x_i - (double)x_j;  dy likewise;                           */
+/*   pair  <=>  dx*dx + dy*dy < cutoff*cutoff   (strict, no fused mult-add)  */
+/* Pairs come out ordered by i, then j.  Returns the number of pairs; only   */
+/* the first cap are stored.                                                 */
+/* ------------------------------------------------------------------------ */
+int64_t oracle_neighbors(int n, const float *xy, double cutoff,
+                         int32_t *pi, int32_t *pj, int64_t cap)
+{
+    const double c2 = cutoff * cutoff;
+    int64_t cnt = 0;
+    for (int i = 0; i < n; ++i) {
+        const double xi = (double)xy[2 * i], yi = (double)xy[2 * i + 1];
+        for (int j = i + 1; j < n; ++j) {
+            const double dx = xi - (double)xy[2 * j];
+            const double dy = yi - (double)xy[2 * j + 1];
+            const double a = dx * dx;
+            const double b = dy * dy;
+            if (a + b < c2) {
+                if (cnt < cap) { pi[cnt] = i; pj[cnt] = j; }
+                ++cnt;
+            }
+        }
+    }
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Limited-memory inverse-Hessian product r = H g.  H is what the BFGS       */
+/* inverse update of Eq. 10-11 gives when applied to the k stored pairs      */
+/* (u = s, v = y), oldest first, starting from H0 = gamma I with gamma =     */
+/* s^T y / y^T y of the newest pair.  Computed by the standard two-loop      */
+/* recursion (Nocedal & Wright, Numerical Optimization, Alg. 7.4), which     */
+/* equals the dense product without forming H.  S and Y hold k rows of       */
+/* length dim, oldest first.  k = 0 gives r = g.                             */
+/* ------------------------------------------------------------------------ */
+void oracle_two_loop(int dim, int k, const double *S, const double *Y,
+                     const double *g, double *r)
+{
+    double alpha[64];
+    double rho[64];
+    for (int d = 0; d < dim; ++d) r[d] = g[d];
+    if (k <= 0) return;
+    for (int i = 0; i < k; ++i) {
+        double sy = 0.0;
+        for (int d = 0; d < dim; ++d) sy += S[(size_t)i * dim + d] * Y[(size_t)i * dim + d];
+        rho[i] = 1.0 / sy;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double a = 0.0;
+        for (int d = 0; d < dim; ++d) a += S[(size_t)i * dim + d] * r[d];
+        a *= rho[i];
+        alpha[i] = a;
+        for (int d = 0; d < dim; ++d) r[d] -= a * Y[(size_t)i * dim + d];
+    }
+    {
+        double sy = 0.0, yy = 0.0;
+        const double *s = S + (size_t)(k - 1) * dim, *y = Y + (size_t)(k - 1) * dim;
+        for (int d = 0; d < dim; ++d) { sy += s[d] * y[d]; yy += y[d] * y[d]; }
+        const double gamma = sy / yy;
+        for (int d = 0; d < dim; ++d) r[d] *= gamma;
+    }
+    for (int i = 0; i < k; ++i) {
+        double b = 0.0;
+        for (int d = 0; d < dim; ++d) b += Y[(size_t)i * dim + d] * r[d];
+        b *= rho[i];
+        for (int d = 0; d < dim; ++d) r[d] += S[(size_t)i * dim + d] * (alpha[i] - b);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Descent parameters and outcome (the oracle's own definitions).            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t m;            /* history pairs kept                               */
+    int32_t max_iter;     /* accepted iterations at most                      */
+    int32_t max_halvings; /* step halvings per line search at most            */
+    int32_t ftol_window;  /* iterations spanned by the relative-decrease test */
+    double c1;            /* sufficient-decrease constant                     */
+    double eps_curv;      /* keep (s,y) only if s^T y > eps_curv * y^T y      */
+    double e_feasible;    /* E below this is feasible                         */
+    double g_tol;         /* ||g||_2 at or below this is stationary           */
+    double ftol;          /* relative decrease over the window (0 = off)      */
+    double rad;           /* circle radius used by the energy                 */
+} oracle_params;
+
+typedef struct {
+    int32_t status;
+    int32_t iters;
+    int32_t evals;
+    int32_t resets;
+    double E;
+    double gnorm;
+} oracle_result;
+
+enum { OR_RUNNING = 0, OR_FEASIBLE = 1, OR_STATIONARY = 2, OR_CONVERGED = 3,
+       OR_STALLED = 4, OR_MAX_ITER = 5, OR_NONFINITE = 6 };
+
+typedef double (*energy_fn)(void *ctx, const double *x, double *g);
+
+typedef struct { int n; double R; double rad; } whole_ctx;
+
+static double whole_energy(void *c, const double *x, double *g)
+{
+    const whole_ctx *w = (const whole_ctx *)c;
+    return oracle_energy_grad(w->n, x, w->R, w->rad, NULL, NULL, g);
+}
+
+static double dot(int d, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* State of one L-BFGS minimisation in FP64. */
+typedef struct {
+    int dim, m, k;
+    double *S, *Y;   /* m rows each, oldest first */
+    double *x, *g, *p, *xt, *gt, *ehist;
+    double E;
+} lbfgs_state;
+
+static int lbfgs_alloc(lbfgs_state *st, int dim, int m, int hist_len)
+{
+    memset(st, 0, sizeof(*st));
+    st->dim = dim; st->m = m; st->k = 0;
+    st->S = calloc((size_t)m * dim, sizeof(double));
+    st->Y = calloc((size_t)m * dim, sizeof(double));
+    st->g = calloc(dim, sizeof(double));
+    st->p = calloc(dim, sizeof(double));
+    st->xt = calloc(dim, sizeof(double));
+    st->gt = calloc(dim, sizeof(double));
+    st->ehist = calloc(hist_len > 0 ? hist_len : 1, sizeof(double));
+    return st->S && st->Y && st->g && st->p && st->xt && st->gt && st->ehist;
+}
+
+static void lbfgs_free(lbfgs_state *st)
+{
+    free(st->S); free(st->Y); free(st->g); free(st->p); free(st->xt);
+    free(st->gt); free(st->ehist);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole-instance L-BFGS descent (Alg. 1 with k = 1 and the limited-memory  */
+/* reading of Eq. 8-11).  One iteration:                                     */
+/*   stop tests on the current point, in this order: non-finite E,          */
+/*     E < e_feasible, ||g||_2 <= g_tol, relative decrease over the last     */
+/*     ftol_window iterations below ftol, iteration budget spent;            */
+/*   p = -H g (two-loop), reset to -g when it is not a descent direction;    */
+/*   alpha0 = 1 with history, 1/max(1,||g||) without;                        */
+/*   halve alpha until E(x+alpha p) <= E + c1 alpha g^T p (max_halvings);    */
+/*   x <- x + alpha p; keep (s,y) when s^T y > eps_curv y^T y, at most m.    */
+/* xy (2n) is updated in place.  trace (nullable, max_iter+1) gets E at the  */
+/* start of every iteration.                                                 */
+/* ------------------------------------------------------------------------ */
+static int run_descent(int dim, double *x, const oracle_params *P, energy_fn f,
+                       void *ctx, oracle_result *res, double *trace)
+{
+    lbfgs_state st;
+    const int W = P->ftol_window > 0 ? P->ftol_window : 1;
+    if (!lbfgs_alloc(&st, dim, P->m, W + 1)) { lbfgs_free(&st); return -1; }
+    double *cand_s = calloc(dim, sizeof(double));
+    double *cand_y = calloc(dim, sizeof(double));
+    if (!cand_s || !cand_y) { free(cand_s); free(cand_y); lbfgs_free(&st); return -1; }
+    st.x = x;
+    int evals = 0, resets = 0, it = 0, status = OR_RUNNING;
+    st.E = f(ctx, x, st.g);
+    ++evals;
+    for (it = 0;; ++it) {
+        const double gn = sqrt(dot(dim, st.g, st.g));
+        if (trace) trace[it] = st.E;
+        if (!isfinite(st.E) || !isfinite(gn)) { status = OR_NONFINITE; break; }
+        if (st.E < P->e_feasible) { status = OR_FEASIBLE; break; }
+        if (gn <= P->g_tol) { status = OR_STATIONARY; break; }
+        if (P->ftol > 0.0 && it >= W) {
+            const double e_old = st.ehist[(it - W) % (W + 1)];
+            if (e_old - st.E <= P->ftol * e_old) { status = OR_CONVERGED; break; }
+        }
+        st.ehist[it % (W + 1)] = st.E;
+        if (it >= P->max_iter) { status = OR_MAX_ITER; break; }
+
+        /* direction */
+        double *p = st.p, *g = st.g, *xt = st.xt, *gt = st.gt;
+        oracle_two_loop(dim, st.k, st.S, st.Y, g, p);
+        for (int d = 0; d < dim; ++d) p[d] = -p[d];
+        double gp = dot(dim, g, p);
+        if (st.k > 0 && !(gp < 0.0)) {
+            st.k = 0;
+            ++resets;
+            for (int d = 0; d < dim; ++d) p[d] = -g[d];
+            gp = dot(dim, g, p);
+        }
+        /* backtracking line search (reading of Eq. 9) */
+        double alpha = st.k > 0 ? 1.0 : 1.0 / (gn > 1.0 ? gn : 1.0);
+        int accepted = 0;
+        double Et = 0.0;
+        for (int h = 0; h <= P->max_halvings; ++h) {
+            for (int d = 0; d < dim; ++d) xt[d] = x[d] + alpha * p[d];
+            Et = f(ctx, xt, gt);
+            ++evals;
+            if (Et <= st.E + P->c1 * alpha * gp) { accepted = 1; break; }
+            alpha *= 0.5;
+        }
+        if (!accepted) { status = OR_STALLED; break; }
+        /* curvature pair (Eq. 10: u = s, v = y) */
+        double sy = 0.0, yy = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            cand_s[d] = xt[d] - x[d];
+            cand_y[d] = gt[d] - g[d];
+            sy += cand_s[d] * cand_y[d];
+            yy += cand_y[d] * cand_y[d];
+        }
+        if (sy > P->eps_curv * yy) {
+            if (st.k == st.m) {
+                memmove(st.S, st.S + dim, sizeof(double) * (size_t)(st.m - 1) * dim);
+                memmove(st.Y, st.Y + dim, sizeof(double) * (size_t)(st.m - 1) * dim);
+                st.k = st.m - 1;
+            }
+            memcpy(st.S + (size_t)st.k * dim, cand_s, sizeof(double) * dim);
+            memcpy(st.Y + (size_t)st.k * dim, cand_y, sizeof(double) * dim);
+            ++st.k;
+        }
+        memcpy(x, xt, sizeof(double) * dim);
+        memcpy(g, gt, sizeof(double) * dim);
+        st.E = Et;
+    }
+    res->status = status;
+    res->iters = it;
+    res->evals = evals;
+    res->resets = resets;
+    res->E = st.E;
+    res->gnorm = sqrt(dot(dim, st.g, st.g));
+    free(cand_s); free(cand_y);
+    lbfgs_free(&st);
+    return 0;
+}
+
+int oracle_descend(int n, double *xy, double R, const oracle_params *P,
+                   oracle_result *res, double *trace)
+{
+    whole_ctx c = { n, R, P->rad };
+    if (P->m < 1 || P->m > 64) return -2;
+    return run_descent(2 * n, xy, P, whole_energy, &c, res, trace);
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP64 feasibility check (Eq. 1-2 through Eq. 5 with unit circles).         */
+/* out[0] = E, out[1] = max_{i<j} d_ij, out[2] = max_i d_i0 (both >= 0),     */
+/* returns 1 if E < tol.  Positions are FP32, promoted exactly.              */
+/* ------------------------------------------------------------------------ */
+int oracle_verify(int n, const float *xy, double R, double tol, double *out)
+{
+    double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double xi = (double)xy[2 * i], yi = (double)xy[2 * i + 1];
+        for (int j = i + 1; j < n; ++j) {
+            const double dx = xi - (double)xy[2 * j];
+            const double dy = yi - (double)xy[2 * j + 1];
+            const double l2 = dx * dx + dy * dy;
+            if (l2 < 4.0) {
+                const double d = 2.0 - sqrt(l2);
+                sp += d * d;
+                if (d > mp) mp = d;
+            }
+        }
+        const double rho = sqrt(xi * xi + yi * yi);
+        const double d0 = rho + 1.0 - R;
+        if (d0 > 0.0) {
+            sc += d0 * d0;
+            if (d0 > mc) mc = d0;
+        }
+    }
+    out[0] = sp + sc;
+    out[1] = mp;
+    out[2] = mc;
+    return (sp + sc) < tol ? 1 : 0;
+}
