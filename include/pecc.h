@@ -1,0 +1,184 @@
+/*
+ * pecc.h -- C ABI of the MI355X (gfx950) penalty-energy descent for packing
+ * equal circles in a circle (PECC), after Zhou, He, Zheng & Li, "Geometric
+ * Batch Optimization for the Packing Equal Circles in a Circle Problem on
+ * Large Scale" (arXiv 2303.02650).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Array arguments are DEVICE pointers to caller-owned memory unless the
+ *    comment says "host".  The library never allocates device memory; where
+ *    a call needs scratch space the caller passes a workspace sized by the
+ *    matching *_workspace_size query.
+ *  * Calls are asynchronous and ordered on the given stream; they return
+ *    after enqueueing.  Nothing is read back to the host.
+ *  * A batch holds B independent instances ("packed" layout).  Instance b
+ *    owns circles offset[b] .. offset[b+1]-1; positions are interleaved
+ *    float pairs xy[2*i], xy[2*i+1] (the solution vector x of Def. 3.2).
+ *    Circle indices in neighbor lists are global over the batch; pairs never
+ *    cross instances.  Container centre is the origin (Sec. 3.1).
+ *  * Every instance must satisfy 0 <= n_b <= PECC_MAX_N and R_b > 0.
+ *    Instances with n_b = 0 are allowed and produce empty results.
+ *  * Return value: PECC_OK or a negative PECC_ERR_* code describing an
+ *    argument or launch problem; pecc_last_error() gives a message for the
+ *    calling thread.  Per-instance numerical outcomes (non-finite input, a
+ *    line search that cannot decrease E, ...) are reported in result
+ *    structs, never as return codes.  Device-side argument problems that
+ *    the host cannot see (n_b > PECC_MAX_N, decreasing offsets) make the
+ *    affected instance report PECC_STATUS_BAD_INSTANCE or an empty result.
+ */
+#ifndef PECC_H
+#define PECC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PECC_OK             0
+#define PECC_ERR_INVALID   -1  /* null pointer, bad size or parameter        */
+#define PECC_ERR_WORKSPACE -2  /* workspace pointer null or too small         */
+#define PECC_ERR_HIP       -3  /* a HIP launch or query failed                 */
+
+#define PECC_MAX_N        1024 /* circles per instance                        */
+#define PECC_MAX_M          10 /* L-BFGS memory                               */
+
+/* Outcome of one descent (pecc_descent_result.status). */
+#define PECC_STATUS_RUNNING      0
+#define PECC_STATUS_FEASIBLE     1  /* FP64 E (unit circles) < e_feasible     */
+#define PECC_STATUS_STATIONARY   2  /* ||g||_2 <= g_tol                        */
+#define PECC_STATUS_CONVERGED    3  /* relative decrease over ftol_window < ftol */
+#define PECC_STATUS_STALLED      4  /* no step length passed the line search    */
+#define PECC_STATUS_MAX_ITER     5  /* iteration budget spent                  */
+#define PECC_STATUS_NONFINITE    6  /* E or g not finite                       */
+#define PECC_STATUS_BAD_INSTANCE 7  /* n_b outside [0, PECC_MAX_N]             */
+
+/* A batch of instances.  Host struct holding device pointers. */
+typedef struct pecc_instances {
+    int32_t        num_instances; /* B >= 1                                     */
+    int32_t        max_n;         /* host: an upper bound of every n_b (<= PECC_MAX_N) */
+    int64_t        total_n;       /* host: offset[B]                            */
+    const int32_t *offset;        /* device [B+1], offset[0] = 0, non-decreasing */
+    const float   *R;             /* device [B], container radius (FP32 copy)   */
+    const double  *R64;           /* device [B] FP64 radius, or NULL: (double)R  */
+} pecc_instances;
+
+/* Thread-local description of the last error on the calling host thread. */
+const char *pecc_last_error(void);
+
+/* Library version string. */
+const char *pecc_version(void);
+
+/* ------------------------------------------------------------------------
+ * Neighbor lists.  Gamma(i) = { j != i : l_ij < l_cut } (Sec. 4.3), built
+ * from a uniform cell grid (counting sort of circles into square cells of
+ * side >= cutoff over [-R, R]^2; clamped cell coordinates) instead of the
+ * paper's scan line.  The predicate is evaluated in FP64 on the FP32
+ * positions, without fused multiply-add:
+ *     dx = (double)x_i - (double)x_j;  dy likewise;
+ *     neighbor  <=>  dx*dx + dy*dy < cutoff*cutoff     (cutoff as double)
+ * so the pair set is a deterministic function of the FP32 input.
+ *
+ * Output is CSR over global circle indices: the list of circle i is
+ * col[row[i]] .. col[row[i+1]-1], ascending.  full = 0 keeps only j > i
+ * (each pair once); full = 1 keeps both orientations (pecc_energy_grad
+ * wants this form).  row has total_n + 1 entries, row[0] = 0.
+ * *num_pairs (device, one int64) receives the number of entries required.
+ * If it exceeds capacity, row is still complete, nothing is written at or
+ * beyond col[capacity], rows ending within the capacity are complete and
+ * the row crossing it holds only part of its entries: re-run with a larger
+ * col.
+ * cell_size <= 0 selects cutoff; otherwise it must be >= cutoff.
+ * Workspace: pecc_build_neighbors_workspace_size().
+ * ------------------------------------------------------------------------ */
+int pecc_build_neighbors_workspace_size(const pecc_instances *inst, size_t *bytes /*host*/);
+int pecc_build_neighbors(const pecc_instances *inst, const float *xy,
+                         double cutoff, float cell_size, int32_t full,
+                         int32_t *row, int32_t *col, int64_t capacity,
+                         int64_t *num_pairs, void *workspace, size_t workspace_bytes,
+                         hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Energy and gradient (Def. 3.1, Def. 3.2; E = sum_{i<j} d_ij^2 +
+ * sum_i d_i0^2) in FP32 over a FULL neighbor list from
+ * pecc_build_neighbors(full = 1).  Pairs outside the list contribute
+ * nothing, so the list must contain every overlapping pair (any list built
+ * with cutoff >= 2*rad at positions each circle has since moved less than
+ * (cutoff - 2*rad)/2 from qualifies).
+ * rad is the circle radius used by the energy (1 for unit circles).
+ * col_len is the number of entries col holds: list entries at or beyond it
+ * are never read, and an instance whose row range leaves [0, col_len) gets
+ * energy NaN.
+ * energy: device [B]; grad: device [2*total_n] or NULL.  Each circle's
+ * gradient is accumulated by one thread in list order (no atomics), so the
+ * result is bitwise reproducible.
+ * ------------------------------------------------------------------------ */
+int pecc_energy_grad(const pecc_instances *inst, const float *xy,
+                     const int32_t *row, const int32_t *col, int64_t col_len, float rad,
+                     float *energy, float *grad, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * L-BFGS descent of E at fixed R (Alg. 1 with the limited-memory reading of
+ * Eq. 8-11 and a backtracking line search in place of the exact one of
+ * Eq. 9), run for every instance of the batch in ONE persistent launch.
+ * Each workgroup takes instances from a queue (largest n first), keeps the
+ * instance's positions, neighbor list and curvature history on chip and
+ * iterates until a stop test holds.  xy is updated in place.
+ * ------------------------------------------------------------------------ */
+typedef struct pecc_descent_params {
+    int32_t m;              /* L-BFGS memory, 1..PECC_MAX_M (10)               */
+    int32_t max_iter;       /* iteration budget (paper: MaxIter = 5000)        */
+    int32_t max_halvings;   /* step halvings per line search (40)              */
+    int32_t ftol_window;    /* iterations spanned by the decrease test (20)    */
+    float   c1;             /* sufficient-decrease constant (1e-4)             */
+    float   eps_curv;       /* keep (s,y) only if s'y > eps_curv * y'y (1e-8)  */
+    float   cutoff;         /* neighbor-list cutoff (2.3)                      */
+    float   skin_half;      /* rebuild when a circle moved more than this (0.15) */
+    float   cell_size;      /* cell side, >= cutoff; <= 0 selects cutoff       */
+    float   g_tol;          /* stop when ||g||_2 <= g_tol (FP32)               */
+    float   ftol;           /* stop when E fell by <= ftol*E over the window; 0 = off */
+    float   contact_margin; /* mu >= 0: the descent works on circles of radius 1+mu */
+    double  e_feasible;     /* FEASIBLE when FP64 E of unit circles < this (1e-20) */
+    double  tau64;          /* sufficient-decrease test in FP64 once E32 < tau64 (1e-4) */
+} pecc_descent_params;
+
+typedef struct pecc_descent_result {
+    int32_t status;         /* PECC_STATUS_*                                   */
+    int32_t iters;          /* accepted iterations                             */
+    int32_t evals;          /* energy/gradient evaluations                     */
+    int32_t rebuilds;       /* neighbor-list rebuilds (the first one included) */
+    int64_t pair_evals;     /* sum over evaluations of listed pairs (i<j)      */
+    float   E32;            /* final FP32 energy of the descent's objective    */
+    float   gnorm;          /* final ||g||_2 (FP32)                             */
+    double  E64;            /* final FP64 energy of unit circles, or -1 if the
+                               descent never entered the FP64 regime           */
+} pecc_descent_result;
+
+/* Fill *p with the defaults listed above. (host) */
+void pecc_descent_params_default(pecc_descent_params *p);
+
+int pecc_lbfgs_descend_workspace_size(const pecc_instances *inst, size_t *bytes /*host*/);
+int pecc_lbfgs_descend(const pecc_instances *inst, float *xy,
+                       const pecc_descent_params *params /*host*/,
+                       pecc_descent_result *out /*device [B]*/,
+                       void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * FP64 feasibility check of Eq. 1-2 through the energy of Def. 3.2 with
+ * unit circles: every pair i<j of each instance is enumerated (no list),
+ * in FP64 on the FP32 positions.  Per instance: energy64 = E,
+ * max_pair_overlap = max_{i<j} d_ij, max_cont_overlap = max_i d_i0 (both
+ * >= 0), feasible = (E < tol).  Any output pointer except energy64 may be
+ * NULL.  Radii come from R64 when given, else from R.
+ * ------------------------------------------------------------------------ */
+int pecc_verify(const pecc_instances *inst, const float *xy, double tol,
+                double *energy64, double *max_pair_overlap, double *max_cont_overlap,
+                int32_t *feasible, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PECC_H */

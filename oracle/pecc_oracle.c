@@ -38,11 +38,33 @@
 /* Returns E; e_pair / e_cont (nullable) get the two sums; grad (nullable,   */
 /* length 2n, interleaved like x) receives dE/dx.                            */
 /* ------------------------------------------------------------------------ */
+static int all_finite_d(int n, const double *xy)
+{
+    for (int i = 0; i < 2 * n; ++i)
+        if (!isfinite(xy[i])) return 0;
+    return 1;
+}
+
+static int all_finite_f(int n, const float *xy)
+{
+    for (int i = 0; i < 2 * n; ++i)
+        if (!isfinite(xy[i])) return 0;
+    return 1;
+}
+
+/* E is a sum over every circle (Eq. 5), so a circle without a finite
+ * position leaves it undefined: E, its parts and g are then NaN. */
 double oracle_energy_grad(int n, const double *xy, double R, double rad,
                           double *e_pair, double *e_cont, double *grad)
 {
     double sp = 0.0, sc = 0.0;
     const double two_r = 2.0 * rad;
+    if (!all_finite_d(n, xy)) {
+        if (grad) for (int i = 0; i < 2 * n; ++i) grad[i] = NAN;
+        if (e_pair) *e_pair = NAN;
+        if (e_cont) *e_cont = NAN;
+        return NAN;
+    }
     if (grad) memset(grad, 0, sizeof(double) * 2 * (size_t)n);
     for (int i = 0; i < n; ++i) {
         const double xi = xy[2 * i], yi = xy[2 * i + 1];
@@ -376,11 +398,16 @@ int oracle_descend(int n, double *xy, double R, const oracle_params *P,
 /* ------------------------------------------------------------------------ */
 /* FP64 feasibility check (Eq. 1-2 through Eq. 5 with unit circles).         */
 /* out[0] = E, out[1] = max_{i<j} d_ij, out[2] = max_i d_i0 (both >= 0),     */
-/* returns 1 if E < tol.  Positions are FP32, promoted exactly.              */
+/* returns 1 if E < tol.  Positions are FP32, promoted exactly.  A non-      */
+/* finite coordinate makes all three NaN and the layout infeasible.          */
 /* ------------------------------------------------------------------------ */
 int oracle_verify(int n, const float *xy, double R, double tol, double *out)
 {
     double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0;
+    if (!all_finite_f(n, xy)) {
+        out[0] = out[1] = out[2] = NAN;
+        return 0;
+    }
     for (int i = 0; i < n; ++i) {
         const double xi = (double)xy[2 * i], yi = (double)xy[2 * i + 1];
         for (int j = i + 1; j < n; ++j) {

@@ -1,0 +1,253 @@
+"""Python binding of libpecc (MI355X penalty-energy descent for PECC).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libpecc.so``.  Tensors are torch tensors on the GPU; the binding
+passes their device pointers and the current torch stream to the C ABI
+declared in ``include/pecc.h`` and raises ``PeccError`` on a non-zero return.
+The library must have been built (``python paper_2303_02650_amd/build.py``);
+importing this package without it raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, asdict, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpecc.so")
+
+PECC_MAX_N = 1024
+PECC_MAX_M = 10
+STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED", 4: "STALLED",
+          5: "MAX_ITER", 6: "NONFINITE", 7: "BAD_INSTANCE"}
+
+
+class PeccError(RuntimeError):
+    pass
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with python paper_2303_02650_amd/build.py")
+_lib = C.CDLL(LIB_PATH)
+
+
+class pecc_instances(C.Structure):
+    _fields_ = [("num_instances", C.c_int32), ("max_n", C.c_int32), ("total_n", C.c_int64),
+                ("offset", C.c_void_p), ("R", C.c_void_p), ("R64", C.c_void_p)]
+
+
+class pecc_descent_params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("max_iter", C.c_int32), ("max_halvings", C.c_int32),
+                ("ftol_window", C.c_int32), ("c1", C.c_float), ("eps_curv", C.c_float),
+                ("cutoff", C.c_float), ("skin_half", C.c_float), ("cell_size", C.c_float),
+                ("g_tol", C.c_float), ("ftol", C.c_float), ("contact_margin", C.c_float),
+                ("e_feasible", C.c_double), ("tau64", C.c_double)]
+
+
+RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("evals", np.int32),
+                         ("rebuilds", np.int32), ("pair_evals", np.int64), ("E32", np.float32),
+                         ("gnorm", np.float32), ("E64", np.float64)])
+assert RESULT_DTYPE.itemsize == 40
+
+_P = C.POINTER
+_sig = {
+    "pecc_last_error": (C.c_char_p, []),
+    "pecc_version": (C.c_char_p, []),
+    "pecc_build_neighbors_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
+    "pecc_build_neighbors": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_float,
+                                       C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pecc_energy_grad": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pecc_descent_params_default": (None, [_P(pecc_descent_params)]),
+    "pecc_lbfgs_descend_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
+    "pecc_lbfgs_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pecc_verify": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PeccError(f"libpecc error {rc}: {_lib.pecc_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def version() -> str:
+    return _lib.pecc_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Instances on the device
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceInstances:
+    """Device copy of a packed batch (offsets, radii) plus host sizes."""
+    offset: torch.Tensor      # int32 [B+1]
+    R: torch.Tensor           # float32 [B]
+    R64: torch.Tensor         # float64 [B]
+    max_n: int
+    total_n: int
+    _c: pecc_instances = field(default=None, repr=False)
+
+    @property
+    def B(self) -> int:
+        return int(self.R.shape[0])
+
+    def c(self) -> pecc_instances:
+        if self._c is None:
+            self._c = pecc_instances(self.B, self.max_n, self.total_n, self.offset.data_ptr(),
+                                     self.R.data_ptr(), self.R64.data_ptr())
+        return self._c
+
+    @staticmethod
+    def from_host(offset, R, device="cuda") -> "DeviceInstances":
+        off = np.asarray(offset, dtype=np.int32)
+        R = np.asarray(R, dtype=np.float64)
+        n = np.diff(off)
+        return DeviceInstances(offset=torch.from_numpy(off).to(device),
+                               R=torch.from_numpy(R.astype(np.float32)).to(device),
+                               R64=torch.from_numpy(R).to(device),
+                               max_n=int(n.max()) if len(n) else 0, total_n=int(off[-1]))
+
+
+# ---------------------------------------------------------------------------
+# C ABI, same names
+# ---------------------------------------------------------------------------
+def pecc_build_neighbors_workspace_size(inst: DeviceInstances) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_build_neighbors_workspace_size(C.byref(inst.c()), C.byref(b)))
+    return b.value
+
+
+def pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, capacity, num_pairs,
+                         workspace, stream=None):
+    _check(_lib.pecc_build_neighbors(C.byref(inst.c()), _ptr(xy), float(cutoff), float(cell_size),
+                                     int(full), _ptr(row), _ptr(col), int(capacity),
+                                     _ptr(num_pairs), _ptr(workspace),
+                                     workspace.numel() * workspace.element_size(),
+                                     _stream(stream)))
+
+
+def pecc_energy_grad(inst, xy, row, col, col_len, rad, energy, grad, stream=None):
+    _check(_lib.pecc_energy_grad(C.byref(inst.c()), _ptr(xy), _ptr(row), _ptr(col),
+                                 int(col_len), float(rad), _ptr(energy), _ptr(grad),
+                                 _stream(stream)))
+
+
+def pecc_lbfgs_descend_workspace_size(inst: DeviceInstances) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_lbfgs_descend_workspace_size(C.byref(inst.c()), C.byref(b)))
+    return b.value
+
+
+def pecc_lbfgs_descend(inst, xy, params: pecc_descent_params, out, workspace, stream=None):
+    _check(_lib.pecc_lbfgs_descend(C.byref(inst.c()), _ptr(xy), C.byref(params), _ptr(out),
+                                   _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                   _stream(stream)))
+
+
+def pecc_verify(inst, xy, tol, energy64, max_pair, max_cont, feasible, stream=None):
+    _check(_lib.pecc_verify(C.byref(inst.c()), _ptr(xy), float(tol), _ptr(energy64),
+                            _ptr(max_pair), _ptr(max_cont), _ptr(feasible), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Conveniences (allocation + the calls above)
+# ---------------------------------------------------------------------------
+@dataclass
+class DescentParams:
+    m: int = 10
+    max_iter: int = 5000
+    max_halvings: int = 40
+    ftol_window: int = 20
+    c1: float = 1e-4
+    eps_curv: float = 1e-8
+    cutoff: float = 2.3
+    skin_half: float = 0.15
+    cell_size: float = 0.0
+    g_tol: float = 1e-6
+    ftol: float = 1e-7
+    contact_margin: float = 0.0
+    e_feasible: float = 1e-20
+    tau64: float = 1e-4
+
+    def c(self) -> pecc_descent_params:
+        return pecc_descent_params(**asdict(self))
+
+
+def default_params() -> DescentParams:
+    p = pecc_descent_params()
+    _lib.pecc_descent_params_default(C.byref(p))
+    return DescentParams(**{k: getattr(p, k) for k, _ in pecc_descent_params._fields_})
+
+
+def build_neighbors(inst: DeviceInstances, xy: torch.Tensor, cutoff: float = 2.3,
+                    cell_size: float = 0.0, full: bool = True, capacity: int | None = None):
+    """Returns (row int32 [total_n+1], col int32 [num_pairs])."""
+    dev = xy.device
+    row = torch.empty(inst.total_n + 1, dtype=torch.int32, device=dev)
+    npairs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(pecc_build_neighbors_workspace_size(inst), dtype=torch.uint8, device=dev)
+    cap = capacity if capacity is not None else max(16, 8 * inst.total_n)
+    col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, cap, npairs, ws)
+    need = int(npairs.item())
+    if need > cap:
+        col = torch.empty(need, dtype=torch.int32, device=dev)
+        pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, need, npairs, ws)
+    return row, col[:need]
+
+
+def energy_grad(inst: DeviceInstances, xy: torch.Tensor, row: torch.Tensor, col: torch.Tensor,
+                rad: float = 1.0, want_grad: bool = True):
+    E = torch.empty(inst.B, dtype=torch.float32, device=xy.device)
+    g = torch.empty_like(xy) if want_grad else None
+    pecc_energy_grad(inst, xy, row, col, col.numel(), rad, E, g)
+    return E, g
+
+
+def lbfgs_descend(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams | None = None,
+                  workspace: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """Descends every instance in place; returns the device result buffer
+    (uint8 [B*40]); ``results()`` turns it into a numpy record array."""
+    P = (params or DescentParams()).c()
+    if out is None:
+        out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=xy.device)
+    if workspace is None:
+        workspace = torch.empty(pecc_lbfgs_descend_workspace_size(inst), dtype=torch.uint8,
+                                device=xy.device)
+    pecc_lbfgs_descend(inst, xy, P, out, workspace)
+    return out
+
+
+def results(out: torch.Tensor) -> np.ndarray:
+    return out.cpu().numpy().view(RESULT_DTYPE)
+
+
+def verify(inst: DeviceInstances, xy: torch.Tensor, tol: float = 1e-20):
+    dev = xy.device
+    e = torch.empty(inst.B, dtype=torch.float64, device=dev)
+    mp = torch.empty_like(e)
+    mc = torch.empty_like(e)
+    f = torch.empty(inst.B, dtype=torch.int32, device=dev)
+    pecc_verify(inst, xy, tol, e, mp, mc, f)
+    return e, mp, mc, f

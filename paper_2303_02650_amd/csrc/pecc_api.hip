@@ -1,0 +1,211 @@
+// C ABI of libpecc: argument validation, workspace sizing, launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/pecc.h"
+#include "pecc_launch.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return PECC_OK;
+    return fail(PECC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_inst(const pecc_instances *in, const char *fn)
+{
+    if (!in) return fail(PECC_ERR_INVALID, "%s: instances is NULL", fn);
+    if (in->num_instances < 1) return fail(PECC_ERR_INVALID, "%s: num_instances must be >= 1", fn);
+    if (!in->offset || !in->R) return fail(PECC_ERR_INVALID, "%s: offset and R must be set", fn);
+    if (in->max_n < 0 || in->max_n > PECC_MAX_N)
+        return fail(PECC_ERR_INVALID, "%s: max_n = %d outside [0, %d]", fn, in->max_n, PECC_MAX_N);
+    if (in->total_n < 0 || in->total_n > 0x7ffffffeLL)
+        return fail(PECC_ERR_INVALID, "%s: total_n = %lld outside [0, 2^31-2]", fn,
+                    (long long)in->total_n);
+    return PECC_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+const char *pecc_last_error(void) { return g_err; }
+
+const char *pecc_version(void) { return "pecc-mi355x 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+int pecc_build_neighbors_workspace_size(const pecc_instances *inst, size_t *bytes)
+{
+    int rc = check_inst(inst, "pecc_build_neighbors_workspace_size");
+    if (rc) return rc;
+    if (!bytes) return fail(PECC_ERR_INVALID, "pecc_build_neighbors_workspace_size: bytes is NULL");
+    *bytes = align256(sizeof(int64_t) * (size_t)inst->num_instances);
+    return PECC_OK;
+}
+
+int pecc_build_neighbors(const pecc_instances *inst, const float *xy, double cutoff,
+                         float cell_size, int32_t full, int32_t *row, int32_t *col,
+                         int64_t capacity, int64_t *num_pairs, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream)
+{
+    const char *fn = "pecc_build_neighbors";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!(cutoff > 0.0) || !isfinite(cutoff)) return fail(PECC_ERR_INVALID, "%s: cutoff must be > 0", fn);
+    if (cell_size > 0.f && (double)cell_size < cutoff)
+        return fail(PECC_ERR_INVALID, "%s: cell_size %g < cutoff %g", fn, cell_size, cutoff);
+    if (!row || !num_pairs) return fail(PECC_ERR_INVALID, "%s: row and num_pairs must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    if (capacity < 0 || capacity > 0x7fffffffLL)
+        return fail(PECC_ERR_INVALID, "%s: capacity outside [0, 2^31-1]", fn);
+    if (capacity > 0 && !col) return fail(PECC_ERR_INVALID, "%s: col is NULL", fn);
+    size_t need = 0;
+    pecc_build_neighbors_workspace_size(inst, &need);
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    const float h = (float)((cell_size > 0.f ? (double)cell_size : cutoff) * (1.0 + 1e-4));
+    return check_hip(pecc::launch_build(inst->offset, inst->R, xy, inst->num_instances,
+                                        inst->total_n, cutoff, h, full ? 1 : 0, row, col,
+                                        capacity, num_pairs, (int64_t *)workspace, stream),
+                     fn);
+}
+
+// ---------------------------------------------------------------------------
+int pecc_energy_grad(const pecc_instances *inst, const float *xy, const int32_t *row,
+                     const int32_t *col, int64_t col_len, float rad, float *energy,
+                     float *grad, hipStream_t stream)
+{
+    const char *fn = "pecc_energy_grad";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!energy) return fail(PECC_ERR_INVALID, "%s: energy is NULL", fn);
+    if (!row) return fail(PECC_ERR_INVALID, "%s: row is NULL", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    if (!(rad > 0.f) || !isfinite(rad)) return fail(PECC_ERR_INVALID, "%s: rad must be > 0", fn);
+    if (col_len < 0) return fail(PECC_ERR_INVALID, "%s: col_len < 0", fn);
+    if (col_len > 0 && !col) return fail(PECC_ERR_INVALID, "%s: col is NULL", fn);
+    return check_hip(pecc::launch_energy_grad(inst->offset, inst->R, xy, inst->num_instances,
+                                              inst->total_n, row, col, col_len, rad, energy,
+                                              grad, stream),
+                     fn);
+}
+
+// ---------------------------------------------------------------------------
+void pecc_descent_params_default(pecc_descent_params *p)
+{
+    if (!p) return;
+    p->m = 10;
+    p->max_iter = 5000;
+    p->max_halvings = 40;
+    p->ftol_window = 20;
+    p->c1 = 1e-4f;
+    p->eps_curv = 1e-8f;
+    p->cutoff = 2.3f;
+    p->skin_half = 0.15f;
+    p->cell_size = 0.f;
+    p->g_tol = 1e-6f;
+    p->ftol = 1e-7f;
+    p->contact_margin = 0.f;
+    p->e_feasible = 1e-20;
+    p->tau64 = 1e-4;
+}
+
+int pecc_lbfgs_descend_workspace_size(const pecc_instances *inst, size_t *bytes)
+{
+    int rc = check_inst(inst, "pecc_lbfgs_descend_workspace_size");
+    if (rc) return rc;
+    if (!bytes) return fail(PECC_ERR_INVALID, "pecc_lbfgs_descend_workspace_size: bytes is NULL");
+    *bytes = align256(sizeof(int32_t) * ((size_t)inst->num_instances + 1));
+    return PECC_OK;
+}
+
+int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
+                       pecc_descent_result *out, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream)
+{
+    const char *fn = "pecc_lbfgs_descend";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    if (p->m < 1 || p->m > PECC_MAX_M) return fail(PECC_ERR_INVALID, "%s: m = %d outside [1, %d]", fn, p->m, PECC_MAX_M);
+    if (p->max_iter < 0) return fail(PECC_ERR_INVALID, "%s: max_iter < 0", fn);
+    if (p->max_halvings < 0 || p->max_halvings > 200) return fail(PECC_ERR_INVALID, "%s: max_halvings outside [0, 200]", fn);
+    if (p->ftol_window < 1 || p->ftol_window > 63) return fail(PECC_ERR_INVALID, "%s: ftol_window outside [1, 63]", fn);
+    if (!(p->c1 > 0.f && p->c1 < 1.f)) return fail(PECC_ERR_INVALID, "%s: c1 outside (0, 1)", fn);
+    if (!(p->eps_curv >= 0.f)) return fail(PECC_ERR_INVALID, "%s: eps_curv < 0", fn);
+    if (!(p->contact_margin >= 0.f && p->contact_margin < 0.5f)) return fail(PECC_ERR_INVALID, "%s: contact_margin outside [0, 0.5)", fn);
+    if (!(p->skin_half > 0.f)) return fail(PECC_ERR_INVALID, "%s: skin_half must be > 0", fn);
+    if (!(p->g_tol >= 0.f) || !(p->ftol >= 0.f)) return fail(PECC_ERR_INVALID, "%s: g_tol and ftol must be >= 0", fn);
+    const double rad = 1.0 + (double)p->contact_margin;
+    // a pair can only be missed if both circles moved by more than half of
+    // the margin between the list cutoff and the overlap distance 2*rad
+    const double room = ((double)p->cutoff - 2.0 * rad) / 2.0;
+    if (!(room > 0.0))
+        return fail(PECC_ERR_INVALID, "%s: cutoff %g must exceed 2*(1+contact_margin)", fn, p->cutoff);
+    if (p->cell_size > 0.f && p->cell_size < p->cutoff)
+        return fail(PECC_ERR_INVALID, "%s: cell_size %g < cutoff %g", fn, p->cell_size, p->cutoff);
+    size_t need = 0;
+    pecc_lbfgs_descend_workspace_size(inst, &need);
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+
+    pecc::DescentArgs a;
+    a.m = p->m;
+    a.max_iter = p->max_iter;
+    a.max_halvings = p->max_halvings;
+    a.ftol_window = p->ftol_window;
+    a.c1 = p->c1;
+    a.eps_curv = p->eps_curv;
+    a.h_req = (float)((p->cell_size > 0.f ? p->cell_size : p->cutoff) * (1.0 + 1e-4));
+    a.g_tol = p->g_tol;
+    a.ftol = p->ftol;
+    a.rad = (float)rad;
+    a.c2 = (double)p->cutoff * (double)p->cutoff;
+    const double skin = (double)p->skin_half < room ? (double)p->skin_half : room;
+    a.skin2 = skin * skin;
+    a.e_feasible = p->e_feasible;
+    a.tau64 = p->tau64;
+    const int grid = pecc::descend_grid(inst->num_instances);
+    return check_hip(pecc::launch_descend(inst->offset, inst->R, xy, inst->num_instances,
+                                          inst->total_n, a, out, (int32_t *)workspace, grid,
+                                          stream),
+                     fn);
+}
+
+// ---------------------------------------------------------------------------
+int pecc_verify(const pecc_instances *inst, const float *xy, double tol, double *energy64,
+                double *max_pair_overlap, double *max_cont_overlap, int32_t *feasible,
+                hipStream_t stream)
+{
+    const char *fn = "pecc_verify";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!energy64) return fail(PECC_ERR_INVALID, "%s: energy64 is NULL", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    return check_hip(pecc::launch_verify(inst->offset, inst->R, inst->R64, xy,
+                                         inst->num_instances, inst->total_n, tol, energy64,
+                                         max_pair_overlap, max_cont_overlap, feasible, stream),
+                     fn);
+}
+
+}  // extern "C"
+
+static_assert(sizeof(pecc_descent_result) == 40, "result layout");
+static_assert(sizeof(pecc_descent_params) == 64, "params layout");

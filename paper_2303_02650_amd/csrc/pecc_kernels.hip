@@ -1,0 +1,375 @@
+// Neighbor-list build, list-based energy/gradient sweep and FP64 verify.
+//
+// One workgroup per instance throughout: an instance (n <= 1024 circles,
+// 8 KB of positions) is staged in LDS once and every access after that is
+// on chip.
+#include "pecc_device.hpp"
+#include "pecc_launch.hpp"
+
+namespace pecc {
+
+constexpr int kBuildBlock = 256;
+
+// Positions of one instance into LDS (coalesced float2 loads).
+template <int BLOCK>
+__device__ __forceinline__ void stage_positions(const float *xy, int off, int n, float2 *pos)
+{
+    const float2 *src = reinterpret_cast<const float2 *>(xy) + off;
+    for (int i = threadIdx.x; i < n; i += BLOCK) pos[i] = src[i];
+}
+
+// Circle range of instance b.  False when the offsets are not a valid
+// range inside [0, total_n] or the instance has more than kMaxN circles.
+__device__ __forceinline__ bool instance_range(const int32_t *offset, int b, int64_t total_n,
+                                               int *off, int *n)
+{
+    const int a = offset[b], e = offset[b + 1];
+    *off = a;
+    *n = e - a;
+    return a >= 0 && e >= a && (int64_t)e <= total_n && e - a <= kMaxN;
+}
+
+// True when circles off .. off+n-1 may be written for an invalid instance.
+__device__ __forceinline__ bool writable_range(int off, int n, int64_t total_n)
+{
+    return off >= 0 && n > 0 && (int64_t)off + n <= total_n;
+}
+
+// ---------------------------------------------------------------------------
+// Build, pass 1: per-circle list length into row[i+1], per-instance total.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBuildBlock) void build_count_kernel(
+    const int32_t *__restrict__ offset, const float *__restrict__ R,
+    const float *__restrict__ xy, int64_t total_n, double c2, float h_req, int full,
+    int32_t *__restrict__ row, int64_t *__restrict__ inst_total)
+{
+    __shared__ float2 pos[kMaxN];
+    __shared__ int cell_start[kMaxCells + 1];
+    __shared__ uint16_t cell_circ[kMaxN];
+    __shared__ uint16_t slot_tmp[kMaxN];
+    __shared__ int scan_tmp[kBuildBlock / kWave + 1];
+    __shared__ int sum_tmp[kBuildBlock / kWave];
+
+    const int b = blockIdx.x;
+    int off, n;
+    if (!instance_range(offset, b, total_n, &off, &n)) {
+        // not a valid instance: an empty list for each of its circles
+        if (writable_range(off, n, total_n))
+            for (int i = threadIdx.x; i < n; i += kBuildBlock) row[off + i + 1] = 0;
+        if (threadIdx.x == 0) inst_total[b] = 0;
+        return;
+    }
+    stage_positions<kBuildBlock>(xy, off, n, pos);
+    __syncthreads();
+    const Grid g = make_grid(R[b], h_req);
+    bin_circles<kBuildBlock>(pos, n, g, cell_start, cell_circ, slot_tmp, scan_tmp);
+    int mine = 0;
+    for (int i = threadIdx.x; i < n; i += kBuildBlock) {
+        const float2 pi = pos[i];
+        int cnt = 0;
+        for_each_candidate(i, pi, g, cell_start, cell_circ, [&](int j) {
+            if ((full || j > i) && near64(pi, pos[j], c2)) ++cnt;
+        });
+        row[off + i + 1] = cnt;
+        mine += cnt;
+    }
+    const int tot = block_sum<kBuildBlock>(mine, sum_tmp);
+    if (threadIdx.x == 0) inst_total[b] = tot;
+}
+
+// Build, pass 2: exclusive scan of the per-instance totals (one workgroup).
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void build_scan_kernel(
+    int64_t *__restrict__ inst_total, int B, int64_t total_n,
+    int32_t *__restrict__ row, int64_t *__restrict__ num_pairs)
+{
+    __shared__ int64_t carry_s;
+    __shared__ int64_t wsum[kScanBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < B; base += kScanBlock) {
+        const int b = base + threadIdx.x;
+        const int64_t v = b < B ? inst_total[b] : 0;
+        int64_t inc = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int64_t t = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) wsum[w] = inc;
+        __syncthreads();
+        int64_t before = 0;
+        for (int k = 0; k < w; ++k) before += wsum[k];
+        int64_t chunk = 0;
+        for (int k = 0; k < kScanBlock / kWave; ++k) chunk += wsum[k];
+        const int64_t carry = carry_s;
+        if (b < B) inst_total[b] = carry + before + inc - v;   // now: base offset
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + chunk;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        num_pairs[0] = carry_s;
+        row[0] = 0;
+        row[total_n] = (int32_t)(carry_s < 0x7fffffffLL ? carry_s : 0x7fffffffLL);
+    }
+}
+
+// Build, pass 3: row offsets and the sorted column indices.
+__global__ __launch_bounds__(kBuildBlock) void build_fill_kernel(
+    const int32_t *__restrict__ offset, const float *__restrict__ R,
+    const float *__restrict__ xy, int64_t total_n, double c2, float h_req, int full,
+    int32_t *__restrict__ row, int32_t *__restrict__ col, int64_t capacity,
+    const int64_t *__restrict__ inst_base)
+{
+    __shared__ float2 pos[kMaxN];
+    __shared__ int cell_start[kMaxCells + 1];
+    __shared__ uint16_t cell_circ[kMaxN];
+    __shared__ uint16_t slot_tmp[kMaxN];
+    __shared__ int scan_tmp[kBuildBlock / kWave + 1];
+    __shared__ int cnt_s[kMaxN];
+    __shared__ int run_s;
+
+    const int b = blockIdx.x;
+    int off, n;
+    const bool ok = instance_range(offset, b, total_n, &off, &n);
+    const int64_t base = inst_base[b];
+    if (!ok) {
+        if (writable_range(off, n, total_n))
+            for (int i = threadIdx.x; i < n; i += kBuildBlock)
+                row[off + i] = (int32_t)(base < 0x7fffffffLL ? base : 0x7fffffffLL);
+        return;
+    }
+    // the counts of pass 1 sit in row[off+1 .. off+n]; read them all first
+    for (int i = threadIdx.x; i < n; i += kBuildBlock) cnt_s[i] = row[off + i + 1];
+    stage_positions<kBuildBlock>(xy, off, n, pos);
+    if (threadIdx.x == 0) run_s = 0;
+    __syncthreads();
+    // exclusive scan of the counts, kBuildBlock circles at a time
+    for (int c0 = 0; c0 < n; c0 += kBuildBlock) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < n ? cnt_s[i] : 0;
+        int tot;
+        const int ex = block_exclusive_scan<kBuildBlock>(v, scan_tmp, &tot);
+        const int run = run_s;
+        __syncthreads();
+        if (i < n) cnt_s[i] = run + ex;           // now: local row start
+        if (threadIdx.x == 0) run_s = run + tot;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += kBuildBlock) {
+        const int64_t r = base + cnt_s[i];
+        row[off + i] = (int32_t)(r < 0x7fffffffLL ? r : 0x7fffffffLL);
+    }
+    const Grid g = make_grid(R[b], h_req);
+    bin_circles<kBuildBlock>(pos, n, g, cell_start, cell_circ, slot_tmp, scan_tmp);
+    for (int i = threadIdx.x; i < n; i += kBuildBlock) {
+        const float2 pi = pos[i];
+        const int64_t start = base + cnt_s[i];
+        int64_t w = start;
+        for_each_candidate(i, pi, g, cell_start, cell_circ, [&](int j) {
+            if ((full || j > i) && near64(pi, pos[j], c2)) {
+                if (w < capacity) col[w] = off + j;
+                ++w;
+            }
+        });
+        // insertion sort of the stored part of this row (rows are short)
+        const int64_t end = w < capacity ? w : capacity;
+        for (int64_t a = start + 1; a < end; ++a) {
+            const int32_t key = col[a];
+            int64_t k = a - 1;
+            while (k >= start && col[k] > key) { col[k + 1] = col[k]; --k; }
+            col[k + 1] = key;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Energy and gradient over a full CSR list (Def. 3.1, Def. 3.2).  Each
+// thread owns circles and sums their pair terms in list order: no atomics.
+// The instance's list segment is staged in LDS when it fits.
+// ---------------------------------------------------------------------------
+constexpr int kSweepBlock = 256;
+constexpr int kColLds = 8192;
+
+__global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
+    const int32_t *__restrict__ offset, const float *__restrict__ R,
+    const float *__restrict__ xy, int64_t total_n, const int32_t *__restrict__ row,
+    const int32_t *__restrict__ col, int64_t col_len, float rad,
+    float *__restrict__ energy, float *__restrict__ grad)
+{
+    __shared__ float2 pos[kMaxN];
+    __shared__ int32_t col_s[kColLds];
+    __shared__ float sum_tmp[kSweepBlock / kWave];
+
+    const int b = blockIdx.x;
+    int off, n;
+    if (!instance_range(offset, b, total_n, &off, &n)) {
+        if (threadIdx.x == 0) energy[b] = __builtin_nanf("");
+        return;
+    }
+    // list entries outside [0, col_len) are never read
+    const int r0 = row[off], r1 = row[off + n];
+    const int len = r1 - r0;
+    const bool sane = r0 >= 0 && len >= 0 && (int64_t)r1 <= col_len;
+    if (!sane) {
+        if (threadIdx.x == 0) energy[b] = __builtin_nanf("");
+        return;
+    }
+    const bool staged = len <= kColLds;
+    stage_positions<kSweepBlock>(xy, off, n, pos);
+    if (staged)
+        for (int k = threadIdx.x; k < len; k += kSweepBlock) col_s[k] = col[r0 + k];
+    __syncthreads();
+    const float Rb = R[b];
+    const float two_r = 2.0f * rad, four_r2 = two_r * two_r;
+    float e = 0.0f;
+    for (int i = threadIdx.x; i < n; i += kSweepBlock) {
+        const float2 pi = pos[i];
+        int a = row[off + i] - r0, z = row[off + i + 1] - r0;
+        a = a < 0 ? 0 : a;
+        z = z > len ? len : z;
+        float gx = 0.0f, gy = 0.0f;
+        for (int k = a; k < z; ++k) {
+            const int j = (staged ? col_s[k] : col[r0 + k]) - off;
+            if ((unsigned)j >= (unsigned)n) continue;   // entry outside the instance
+            const float2 pj = pos[j];
+            const float dx = pi.x - pj.x, dy = pi.y - pj.y;
+            const float l2 = dx * dx + dy * dy;
+            if (l2 < four_r2) {
+                const float l = sqrtf(l2);
+                const float d = two_r - l;
+                if (j > i) e += d * d;
+                if (l > 0.0f) {
+                    const float kf = -2.0f * d / l;
+                    gx += kf * dx;
+                    gy += kf * dy;
+                }
+            }
+        }
+        const float rho = sqrtf(pi.x * pi.x + pi.y * pi.y);
+        const float d0 = rho + rad - Rb;
+        if (d0 > 0.0f) {
+            e += d0 * d0;
+            if (rho > 0.0f) {
+                const float kc = 2.0f * d0 / rho;
+                gx += kc * pi.x;
+                gy += kc * pi.y;
+            }
+        }
+        // E sums over every circle: a non-finite position makes it NaN
+        if (!(isfinite(pi.x) && isfinite(pi.y))) e = __builtin_nanf("");
+        if (grad) reinterpret_cast<float2 *>(grad)[off + i] = make_float2(gx, gy);
+    }
+    const float tot = block_sum<kSweepBlock>(e, sum_tmp);
+    if (threadIdx.x == 0) energy[b] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 verify: every pair of the instance once.  Circle i is paired with
+// the next floor((n-1)/2) circles cyclically (and, for even n, with i+n/2
+// when i < n/2), which visits each unordered pair exactly once and gives
+// every thread the same amount of work.
+// ---------------------------------------------------------------------------
+constexpr int kVerifyBlock = 256;
+
+__global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
+    const int32_t *__restrict__ offset, const float *__restrict__ R,
+    const double *__restrict__ R64, const float *__restrict__ xy, int64_t total_n, double tol,
+    double *__restrict__ energy64, double *__restrict__ max_pair,
+    double *__restrict__ max_cont, int32_t *__restrict__ feasible)
+{
+    __shared__ float2 pos[kMaxN];
+    __shared__ double sum_tmp[kVerifyBlock / kWave];
+
+    const int b = blockIdx.x;
+    int off, n;
+    if (!instance_range(offset, b, total_n, &off, &n)) {
+        if (threadIdx.x == 0) {
+            energy64[b] = __builtin_nan("");
+            if (max_pair) max_pair[b] = __builtin_nan("");
+            if (max_cont) max_cont[b] = __builtin_nan("");
+            if (feasible) feasible[b] = 0;
+        }
+        return;
+    }
+    stage_positions<kVerifyBlock>(xy, off, n, pos);
+    __syncthreads();
+    const double Rb = R64 ? R64[b] : (double)R[b];
+    double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0;
+    const int half = (n - 1) / 2;
+    const bool even = (n & 1) == 0;
+    for (int i = threadIdx.x; i < n; i += kVerifyBlock) {
+        const double xi = pos[i].x, yi = pos[i].y;
+        const int extra = (even && i < n / 2) ? 1 : 0;
+        for (int t = 1; t <= half + extra; ++t) {
+            int j = i + t;
+            if (j >= n) j -= n;
+            const double dx = __dsub_rn(xi, (double)pos[j].x);
+            const double dy = __dsub_rn(yi, (double)pos[j].y);
+            const double l2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+            if (l2 < 4.0) {
+                const double d = __dsub_rn(2.0, sqrt(l2));
+                sp = __dadd_rn(sp, __dmul_rn(d, d));
+                mp = fmax(mp, d);
+            }
+        }
+        const double rho = sqrt(__dadd_rn(__dmul_rn(xi, xi), __dmul_rn(yi, yi)));
+        const double d0 = __dsub_rn(__dadd_rn(rho, 1.0), Rb);
+        if (d0 > 0.0) {
+            sc = __dadd_rn(sc, __dmul_rn(d0, d0));
+            mc = fmax(mc, d0);
+        }
+        if (!(isfinite(xi) && isfinite(yi))) sc = __builtin_nan("");
+    }
+    const double Ep = block_sum<kVerifyBlock>(sp, sum_tmp);
+    const double Ec = block_sum<kVerifyBlock>(sc, sum_tmp);
+    const double Mp = block_max<kVerifyBlock>(mp, sum_tmp);
+    const double Mc = block_max<kVerifyBlock>(mc, sum_tmp);
+    if (threadIdx.x == 0) {
+        const double E = Ep + Ec;
+        const bool bad = E != E;     // a non-finite coordinate
+        energy64[b] = E;
+        if (max_pair) max_pair[b] = bad ? E : Mp;
+        if (max_cont) max_cont[b] = bad ? E : Mc;
+        if (feasible) feasible[b] = E < tol ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_build(const int32_t *offset, const float *R, const float *xy, int B,
+                        int64_t total_n, double cutoff, float h_req, int full,
+                        int32_t *row, int32_t *col, int64_t capacity, int64_t *num_pairs,
+                        int64_t *inst_total, hipStream_t s)
+{
+    const double c2 = cutoff * cutoff;
+    build_count_kernel<<<B, kBuildBlock, 0, s>>>(offset, R, xy, total_n, c2, h_req, full, row,
+                                                 inst_total);
+    build_scan_kernel<<<1, kScanBlock, 0, s>>>(inst_total, B, total_n, row, num_pairs);
+    build_fill_kernel<<<B, kBuildBlock, 0, s>>>(offset, R, xy, total_n, c2, h_req, full, row, col,
+                                                capacity, inst_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_grad(const int32_t *offset, const float *R, const float *xy, int B,
+                              int64_t total_n, const int32_t *row, const int32_t *col,
+                              int64_t col_len, float rad, float *energy, float *grad,
+                              hipStream_t s)
+{
+    energy_grad_kernel<<<B, kSweepBlock, 0, s>>>(offset, R, xy, total_n, row, col, col_len, rad,
+                                                 energy, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const int32_t *offset, const float *R, const double *R64,
+                         const float *xy, int B, int64_t total_n, double tol, double *e64,
+                         double *mp, double *mc, int32_t *feas, hipStream_t s)
+{
+    verify_kernel<<<B, kVerifyBlock, 0, s>>>(offset, R, R64, xy, total_n, tol, e64, mp, mc, feas);
+    return hipGetLastError();
+}
+
+}  // namespace pecc

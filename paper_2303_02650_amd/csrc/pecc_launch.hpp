@@ -1,0 +1,37 @@
+// Host-side launchers of the library's kernels (called by the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pecc {
+
+hipError_t launch_build(const int32_t *offset, const float *R, const float *xy, int B,
+                        int64_t total_n, double cutoff, float h_req, int full,
+                        int32_t *row, int32_t *col, int64_t capacity, int64_t *num_pairs,
+                        int64_t *inst_total, hipStream_t s);
+
+hipError_t launch_energy_grad(const int32_t *offset, const float *R, const float *xy, int B,
+                              int64_t total_n, const int32_t *row, const int32_t *col,
+                              int64_t col_len, float rad, float *energy, float *grad,
+                              hipStream_t s);
+
+hipError_t launch_verify(const int32_t *offset, const float *R, const double *R64,
+                         const float *xy, int B, int64_t total_n, double tol, double *e64,
+                         double *mp, double *mc, int32_t *feas, hipStream_t s);
+
+// Descent constants as the kernels use them (derived from the public params).
+struct DescentArgs {
+    int m, max_iter, max_halvings, ftol_window;
+    float c1, eps_curv, h_req, g_tol, ftol, rad;
+    double c2, skin2, e_feasible, tau64;
+};
+
+struct DescentResultDev;  // layout-identical to pecc_descent_result
+
+hipError_t launch_descend(const int32_t *offset, const float *R, float *xy, int B,
+                          int64_t total_n, const DescentArgs &a, void *out,
+                          int32_t *queue, int grid, hipStream_t s);
+
+int descend_grid(int B);   // persistent workgroups to launch for B instances
+
+}  // namespace pecc

@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/pecc.h declares, and rejects bad arguments before any GPU work
+(no compute call is made here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pecc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pecc_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2303_02650_amd as P
+    return P
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(P._lib, name), name
+        assert name in P.EXPORTED, f"binding lacks {name}"
+
+
+def test_version(P):
+    assert "gfx950" in P.version()
+
+
+def _fake_inst(P, B=2, max_n=10, total_n=20):
+    # non-null dummy device pointers: validation must fail before any use
+    return P.pecc_instances(B, max_n, total_n, 0x1000, 0x2000, 0)
+
+
+def _rc(fn, *args):
+    return fn(*args)
+
+
+def test_descend_rejects_bad_params(P):
+    inst = _fake_inst(P)
+    out = C.c_void_p(0x3000)
+    ws = C.c_void_p(0x4000)
+    for field, bad in [("m", 0), ("m", 11), ("max_iter", -1), ("ftol_window", 0),
+                       ("ftol_window", 64), ("c1", 0.0), ("c1", 1.0), ("contact_margin", -1.0),
+                       ("skin_half", 0.0), ("cutoff", 1.9), ("cell_size", 1.0)]:
+        p = P.DescentParams()
+        setattr(p, field, bad)
+        rc = P._lib.pecc_lbfgs_descend(C.byref(inst), C.c_void_p(0x5000), C.byref(p.c()), out, ws,
+                                       1 << 20, None)
+        assert rc == -1, (field, bad, rc)
+        assert len(P._lib.pecc_last_error()) > 0
+    # workspace too small
+    p = P.DescentParams().c()
+    rc = P._lib.pecc_lbfgs_descend(C.byref(inst), C.c_void_p(0x5000), C.byref(p), out, ws, 4, None)
+    assert rc == -2
+    # margin that eats the whole skin
+    p = P.DescentParams(contact_margin=0.2).c()
+    rc = P._lib.pecc_lbfgs_descend(C.byref(inst), C.c_void_p(0x5000), C.byref(p), out, ws, 1 << 20,
+                                   None)
+    assert rc == -1 and b"cutoff" in P._lib.pecc_last_error()
+
+
+def test_instances_validation(P):
+    p = P.DescentParams().c()
+    for inst in [P.pecc_instances(0, 10, 20, 0x1000, 0x2000, 0),
+                 P.pecc_instances(2, 2000, 20, 0x1000, 0x2000, 0),
+                 P.pecc_instances(2, 10, -1, 0x1000, 0x2000, 0),
+                 P.pecc_instances(2, 10, 20, 0, 0x2000, 0),
+                 P.pecc_instances(2, 10, 20, 0x1000, 0, 0)]:
+        rc = P._lib.pecc_lbfgs_descend(C.byref(inst), C.c_void_p(0x5000), C.byref(p),
+                                       C.c_void_p(0x3000), C.c_void_p(0x4000), 1 << 20, None)
+        assert rc == -1
+    assert P._lib.pecc_lbfgs_descend(None, None, None, None, None, 0, None) == -1
+
+
+def test_build_and_sweep_validation(P):
+    inst = _fake_inst(P)
+    size = C.c_size_t()
+    assert P._lib.pecc_build_neighbors_workspace_size(C.byref(inst), C.byref(size)) == 0
+    assert size.value >= 16
+    args = dict(xy=C.c_void_p(0x10), cutoff=2.3, cell=0.0, full=1, row=C.c_void_p(0x20),
+                col=C.c_void_p(0x30), cap=100, npairs=C.c_void_p(0x40), ws=C.c_void_p(0x50),
+                wsb=size.value)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return P._lib.pecc_build_neighbors(C.byref(inst), a["xy"], a["cutoff"], a["cell"],
+                                           a["full"], a["row"], a["col"], a["cap"], a["npairs"],
+                                           a["ws"], a["wsb"], None)
+    assert call(cutoff=0.0) == -1
+    assert call(cell=1.0) == -1
+    assert call(row=None) == -1
+    assert call(cap=-1) == -1
+    assert call(col=None) == -1
+    assert call(wsb=1) == -2
+    assert call(ws=None) == -2
+    # energy/grad
+    E = C.c_void_p(0x60)
+    f = P._lib.pecc_energy_grad
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 0.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), None, C.c_void_p(0x30), 10, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), None, 10, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), -1, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 1.0, None, None, None) == -1
+    # verify
+    assert P._lib.pecc_verify(C.byref(inst), C.c_void_p(0x10), 1e-20, None, None, None, None, None) == -1
+
+
+def test_default_params_match_header(P):
+    d = P.default_params()
+    assert d.m == 10 and d.max_iter == 5000 and d.max_halvings == 40
+    assert abs(d.cutoff - 2.3) < 1e-6 and abs(d.skin_half - 0.15) < 1e-7
+    assert d.e_feasible == 1e-20 and d.tau64 == 1e-4

@@ -419,3 +419,13 @@ def test_descent_sufficient_decrease_with_large_c1():
         assert len(tr) > 25
         assert (np.diff(tr) <= 0).all()
         assert (np.diff(tr[:20]) < 0).all()
+
+
+def test_nonfinite_position_leaves_energy_undefined():
+    xy = synth.disk_uniform(6, 4.0, synth.rng_for(4))
+    xy[3, 1] = np.inf
+    E, Ep, Ec, g = oracle.energy_grad(xy, 4.0)
+    assert np.isnan(E) and np.isnan(g).all()
+    xy[3, 1] = np.nan
+    v = oracle.verify(xy.astype(np.float32), 4.0)
+    assert np.isnan(v["E"]) and not v["feasible"]
