@@ -1,0 +1,275 @@
+#!/usr/bin/env python3
+"""Benchmark of the PECC penalty-energy descent on one MI355X.
+
+A step is one pass of the whole hot path over one batch: 256 random starts
+of n = 1000 unit circles in a container of radius R = 34.6 (centres uniform
+in the disk of radius R - 1, independent children of seed 1) are reset into
+the work buffer, every instance descends with L-BFGS in one persistent
+launch (cell-grid neighbor lists, skin-triggered rebuilds, FP32 sweep, FP64
+sufficient-decrease test near E = 0) and the FP64 verify checks every final
+layout.  The step is captured once as HIP graphs and replayed.
+
+Printed JSON line: descents/s of the batched path (value), the plain
+single-instance path on a sample of the same instances, pair-evals/s, the
+fraction of descents that end FP64-feasible (E < 1e-20), the roofline of the
+descent kernel and of the standalone list sweep at an HBM-sized batch, and
+the FP64 oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
+FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, TFLOP/s
+
+N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=BATCH)
+    ap.add_argument("--max-iter", type=int, default=5000)
+    ap.add_argument("--plain-sample", type=int, default=8, help="instances timed one call each")
+    ap.add_argument("--sweep-batch", type=int, default=65536, help="instances in the HBM sweep test")
+    ap.add_argument("--sweep-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep roofline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance path")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
+    ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
+    return ap.parse_args()
+
+
+def descent_params(P, max_iter):
+    # FP32 working-precision stop: relative decrease below 1e-7 over 20
+    # iterations, or ||g||_2 <= 1e-6; a contact margin of 4 FP32 ulps of the
+    # coordinates lets FP32 descents aim inside the FP64-feasible set.
+    return P.DescentParams(max_iter=max_iter, g_tol=1e-6, ftol=1e-7, ftol_window=20,
+                           contact_margin=1e-5, tau64=1e-4)
+
+
+def algorithmic_flops(res, n, m):
+    """Flops the method needs for the recorded work:
+    10 per listed pair (i<j) and 10 per circle per evaluation, and the
+    L-BFGS two-loop (16 m n) plus the curvature update (8 n) per iteration."""
+    return float((10.0 * res["pair_evals"] + 10.0 * n * res["evals"]
+                  + (16.0 * m * n + 8.0 * n) * res["iters"]).sum())
+
+
+def _oracle_descent(args):
+    xy, R, max_iter = args
+    import oracle
+    P = oracle.DescentParams(max_iter=max_iter, g_tol=1e-12, ftol=1e-7, ftol_window=20)
+    t0 = time.perf_counter()
+    _, res, _ = oracle.descend(xy.astype(np.float64), R, P)
+    return time.perf_counter() - t0, res
+
+
+def run_cpu_baseline(inst, max_iter, sample, cores):
+    import multiprocessing as mp
+    import oracle
+    oracle.lib()   # built before the pool forks
+    jobs = [(inst.instance(b), float(inst.R[b]), max_iter) for b in range(sample)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        out = pool.map(_oracle_descent, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    iters = sum(r["iters"] for _, r in out)
+    evals = sum(r["evals"] for _, r in out)
+    n = inst.instance(0).shape[0]
+    feas = sum(r["status"] == "FEASIBLE" for _, r in out)
+    return {"value": sample / wall, "unit": "descents/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{sample} of the {inst.B} n={n} R={inst.R[0]} starts, FP64 brute-force "
+                       f"L-BFGS descents over {cores} processes; {iters} iterations, "
+                       f"{evals} evaluations of n(n-1)/2 = {n * (n - 1) // 2} pairs; "
+                       f"{feas} feasible; wall {wall:.1f} s"),
+            "pair_evals_per_s_bruteforce": evals * n * (n - 1) / 2 / wall}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(instances are independent: a multi-GPU run would shard the batch with no "
+              "exchange)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2303_02650_amd as P
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print(f"[bench] {P.version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+
+    inst = synth.C2(a.batch)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    xy0 = torch.from_numpy(inst.xy.reshape(-1)).to(dev)
+    xy = torch.empty_like(xy0)
+    params = descent_params(P, a.max_iter)
+    ws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device=dev)
+    out = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    e64 = torch.empty(d.B, dtype=torch.float64, device=dev)
+    mp_ = torch.empty_like(e64)
+    mc_ = torch.empty_like(e64)
+    feas = torch.empty(d.B, dtype=torch.int32, device=dev)
+    Pc = params.c()
+
+    def descend_once():
+        xy.copy_(xy0)
+        P.pecc_lbfgs_descend(d, xy, Pc, out, ws)
+
+    def verify_once():
+        P.pecc_verify(d, xy, 1e-20, e64, mp_, mc_, feas)
+
+    # eager warm-up (also primes the library's device queries), then capture
+    descend_once(); verify_once()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    g_desc, g_ver = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g_desc, stream=side):
+            descend_once()
+        with torch.cuda.graph(g_ver, stream=side):
+            verify_once()
+    torch.cuda.synchronize()
+    for _ in range(a.warmup):
+        g_desc.replay(); g_ver.replay()
+    torch.cuda.synchronize()
+    print(f"[bench] warm-up done ({a.warmup} steps)", file=sys.stderr, flush=True)
+
+    # ---- timed region: K steps --------------------------------------------
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1, e2 in evs:
+        e0.record(stream)
+        g_desc.replay()
+        e1.record(stream)
+        g_ver.replay()
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    desc_ms = [e0.elapsed_time(e1) for e0, e1, _ in evs]
+    ver_ms = [e1.elapsed_time(e2) for _, e1, e2 in evs]
+    ms_per_step = wall * 1e3 / a.steps
+    res = P.results(out)
+    f = feas.cpu().numpy()
+    value = a.batch / (ms_per_step / 1e3)
+    pair_evals = int(res["pair_evals"].sum())
+    status_counts = {P.STATUS[s]: int((res["status"] == s).sum()) for s in np.unique(res["status"])}
+    print(f"[bench] timed {a.steps} steps: {ms_per_step:.2f} ms/step, descent kernel "
+          f"{np.mean(desc_ms):.2f} ms, verify {np.mean(ver_ms):.3f} ms; status {status_counts}",
+          file=sys.stderr, flush=True)
+
+    # roofline of the descent kernel: algorithmic flops / kernel time
+    flops = algorithmic_flops(res, N_CIRCLES, params.m)
+    t_desc = float(np.mean(desc_ms)) / 1e3
+    achieved_tf = flops / t_desc / 1e12
+    roof = {"kernel": "lbfgs_descend_kernel", "bound": "alu", "achieved": achieved_tf,
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
+            "traffic": None,
+            "per_launch_flops": flops, "avg_launch_ms": t_desc * 1e3}
+
+    line = {
+        "metric": "L-BFGS descents/sec at n=1000 (batched FP32, persistent launch), to E<1e-20 or convergence",
+        "value": value, "unit": "descents/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (f64 verify and near-zero line search)",
+        "data": "synthetic",
+        "config": {"workload": f"{a.batch} random starts, n={N_CIRCLES}, R={R_C2}, m=10, "
+                               f"max_iter={a.max_iter}, cutoff 2.3, skin 0.15",
+                   "instances": a.batch, "n": N_CIRCLES, "R": R_C2},
+        "pair_evals_per_s": pair_evals / (ms_per_step / 1e3),
+        "feasible_fraction": float(f.mean()),
+        "status_counts": status_counts,
+        "iters_mean": float(res["iters"].mean()), "evals_mean": float(res["evals"].mean()),
+        "E64_final_mean": float(e64.cpu().numpy().mean()),
+        "roofline": roof,
+    }
+
+    # ---- plain single-instance path (one call per instance, no graph) ------
+    if not a.no_plain:
+        k = min(a.plain_sample, a.batch)
+        subs = []
+        for b in range(k):
+            one = synth.pack([inst.instance(b)], [inst.R[b]])
+            db = P.DeviceInstances.from_host(one.offset, one.R)
+            x0 = torch.from_numpy(one.xy.reshape(-1)).to(dev)
+            subs.append((db, x0, torch.empty_like(x0),
+                         torch.empty(P.pecc_lbfgs_descend_workspace_size(db), dtype=torch.uint8, device=dev),
+                         torch.empty(P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)))
+        for db, x0, xw, wsb, ob in subs[:1]:       # warm-up
+            xw.copy_(x0); P.pecc_lbfgs_descend(db, xw, Pc, ob, wsb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for db, x0, xw, wsb, ob in subs:
+            xw.copy_(x0)
+            P.pecc_lbfgs_descend(db, xw, Pc, ob, wsb)
+            torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - t0
+        plain_rate = k / plain_wall
+        line["plain_descents_per_s"] = plain_rate
+        line["batched_over_plain"] = value / plain_rate
+        line["plain_sample"] = k
+        print(f"[bench] plain: {k} descents in {plain_wall:.3f} s", file=sys.stderr, flush=True)
+
+    # ---- standalone list sweep at an HBM-sized batch -----------------------
+    if not a.no_sweep:
+        reps = a.sweep_batch // a.batch
+        big = synth.pack([inst.instance(b) for b in range(a.batch)] * reps, list(inst.R) * reps)
+        dbig = P.DeviceInstances.from_host(big.offset, big.R)
+        xb = torch.from_numpy(big.xy.reshape(-1)).to(dev)
+        row, col = P.build_neighbors(dbig, xb, 2.3, 0.0, True)
+        E = torch.empty(dbig.B, dtype=torch.float32, device=dev)
+        g = torch.empty_like(xb)
+        for _ in range(3):
+            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), 1.0, E, g)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.sweep_reps):
+            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), 1.0, E, g)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / a.sweep_reps
+        tn = dbig.total_n
+        bytes_alg = 8 * tn + 8 * tn + 4 * (tn + dbig.B) + 4 * col.numel() + 4 * dbig.B
+        gbs = bytes_alg / t / 1e9
+        line["roofline_sweep"] = {
+            "kernel": "energy_grad_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "per_launch_bytes": bytes_alg, "avg_launch_ms": t * 1e3,
+            "instances": dbig.B, "listed_pairs": int(col.numel() // 2),
+            "pair_evals_per_s": (col.numel() // 2) / t}
+        print(f"[bench] sweep: {dbig.B} instances, {bytes_alg / 1e9:.2f} GB in {t * 1e3:.3f} ms "
+              f"= {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+        del big, dbig, xb, row, col, E, g
+
+    # ---- FP64 oracle on the host cores (bounded sample) --------------------
+    if not a.no_cpu:
+        cores = a.cpu_cores or max(1, min(16, len(os.sched_getaffinity(0))))
+        sample = min(a.cpu_sample or a.batch, a.batch)
+        print(f"[bench] oracle CPU baseline: {sample} descents on {cores} processes ...",
+              file=sys.stderr, flush=True)
+        line["cpu_baseline"] = run_cpu_baseline(inst, a.max_iter, sample, cores)
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

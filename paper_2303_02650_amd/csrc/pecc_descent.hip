@@ -567,11 +567,12 @@ int descend_grid(int B)
             cus <= 0)
             cus = 256;
     }
-    int per_cu = 1;
-    int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lbfgs_descend_kernel, kDB, 0) ==
-            hipSuccess && occ > 0)
-        per_cu = occ;
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int occ = 0;
+        per_cu = (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lbfgs_descend_kernel, kDB, 0) ==
+                      hipSuccess && occ > 0) ? occ : 1;
+    }
     const int cap = cus * per_cu;
     return B < cap ? B : cap;
 }
