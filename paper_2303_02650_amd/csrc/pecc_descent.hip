@@ -27,7 +27,7 @@ constexpr int kDW = kDB / kWave;          // waves per workgroup
 constexpr int kCPT = kMaxN / kDB;         // circles per thread
 constexpr int kMM = 10;                   // history slots (max m)
 constexpr int kNB = 2 * kMM + 1;          // basis size: s_0..s_9, y_0..y_9, g
-constexpr int kListCap = 12 * kMaxN;      // neighbor entries held in LDS
+constexpr int kEll = 24;                  // neighbor slots per circle (ELL list)
 constexpr int kG = 2 * kMM;               // basis index of g
 
 // Slots of the fused reduction.  gt: trial gradient, sc = xt - x, yc = gt - g.
@@ -51,9 +51,8 @@ struct DescentShared {
     int cell_start[kMaxCells + 1];
     uint16_t cell_circ[kMaxN];
     uint16_t slot_tmp[kMaxN];
-    uint16_t list[kListCap];
-    uint16_t list_beg[kMaxN];
-    uint16_t list_end[kMaxN];
+    uint16_t list[kEll][kMaxN];    // slot-major: lanes read consecutive entries
+    uint8_t  list_n[kMaxN];
     float red[2][kDW][kWave];
     double red64[2][kDW][2];
     float Bm[2][kNB * kNB];
@@ -61,6 +60,7 @@ struct DescentShared {
     uint16_t bsrc[2][kNB * kNB];   // Gram update sources, see gram_source
     int scan_tmp[kDW + 1];
     int flag[2];
+    int over;                      // a circle had more than kEll neighbors
     int work;
 };
 
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         }
         const float R = Rv[b];
         const float rad = A.rad, two_r = 2.0f * rad, four_r2 = two_r * two_r;
+        const float four_r2_band = four_r2 * (1.0f + 1e-5f);
         const double rad64 = (double)rad, two_r64 = 2.0 * rad64, four_r2_64 = two_r64 * two_r64;
         const double R64 = (double)R;
         const Grid grid = make_grid(R, A.h_req);
@@ -360,9 +361,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         int cur = 0;                   // Bm buffer in use
         int tcount = 0;                // evaluations so far (flag parity)
         bool overflow = false;         // list did not fit: sweep the cell grid
-        int half_pairs = 0;            // listed pairs i<j since the last rebuild
+        int half_mine[kCPT] = {};      // listed pairs i<j of this thread's circles
+        int64_t pair_mine = 0;         // summed over evaluations
         int rebuilds = 0, evals = 0;
-        int64_t pair_evals = 0;
         bool fp64 = false;
         double E64o = 0.0, E64t = -1.0;   // FP64 energies (objective / unit circles)
         float E = 0.0f, gp = 0.f, alpha = 0.f;
@@ -394,6 +395,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (tid == 0) sh.flag[par ^ 1] = 0;
             if (sh.flag[par]) {
                 // ---- neighbor list rebuild at the positions in sh.pos -------
+                if (tid == 0) sh.over = 0;    // set again below only after bin_circles' barriers
                 bin_circles<kDB>(sh.pos, n, grid, sh.cell_start, sh.cell_circ, sh.slot_tmp,
                                  sh.scan_tmp);
                 // ascending circle index inside every cell: lists (cells in
@@ -409,13 +411,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                 }
                 __syncthreads();
-                int cnt[kCPT];
-                int mine = 0;
+                // one pass: every circle writes its neighbors into its own
+                // kEll slots; more than kEll switches this list epoch to
+                // sweeping the cell grid instead
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = tid + c * kDB;
-                    int m = 0;
                     if (act[c]) {
+                        int m = 0, up = 0;
                         const int cx = cell_coord(xt[c].x, grid), cy = cell_coord(xt[c].y, grid);
                         const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
                         const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
@@ -424,47 +427,27 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             const int z = sh.cell_start[yy * grid.nc + x1 + 1];
                             for (int t = a; t < z; ++t) {
                                 const int j = sh.cell_circ[t];
-                                if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) ++m;
-                            }
-                        }
-                    }
-                    cnt[c] = m;
-                    mine += m;
-                }
-                int total;
-                int start = block_exclusive_scan<kDB>(mine, sh.scan_tmp, &total);
-                overflow = total > kListCap;
-                half_pairs = total / 2;
-#pragma unroll
-                for (int c = 0; c < kCPT; ++c) {
-                    const int i = tid + c * kDB;
-                    if (act[c]) {
-                        sh.list_beg[i] = (uint16_t)(overflow ? 0 : start);
-                        sh.list_end[i] = (uint16_t)(overflow ? 0 : start + cnt[c]);
-                        if (!overflow) {
-                            int w = start;
-                            const int cx = cell_coord(xt[c].x, grid), cy = cell_coord(xt[c].y, grid);
-                            const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
-                            const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
-                            for (int yy = y0; yy <= y1; ++yy) {
-                                const int a = sh.cell_start[yy * grid.nc + x0];
-                                const int z = sh.cell_start[yy * grid.nc + x1 + 1];
-                                for (int t = a; t < z; ++t) {
-                                    const int j = sh.cell_circ[t];
-                                    if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) sh.list[w++] = (uint16_t)j;
+                                if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) {
+                                    if (m < kEll) sh.list[m][i] = (uint16_t)j;
+                                    ++m;
+                                    up += j > i;
                                 }
                             }
                         }
+                        if (m > kEll) sh.over = 1;
+                        sh.list_n[i] = (uint8_t)(m < kEll ? m : kEll);
+                        half_mine[c] = up;
                         xr[c] = xt[c];
                     }
-                    start += cnt[c];
                 }
                 ++rebuilds;
                 __syncthreads();
+                overflow = sh.over != 0;
             }
             ++tcount;
             ++evals;
-            pair_evals += half_pairs;
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) pair_mine += half_mine[c];
             // ---- pair sweep: energy and gradient of this thread's circles ----
             float e = 0.f;
             double eo = 0.0, et = 0.0;
@@ -478,16 +461,19 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     float ec = 0.f;
                     double eoc = 0.0, etc = 0.0;
                     if (!overflow) {
-                        const int a = sh.list_beg[i], z = sh.list_end[i];
-                        for (int t = a; t < z; ++t) {
-                            const int j = sh.list[t];
-                            pair_term32(q, sh.pos[j], j > i, two_r, four_r2, ec, gx, gy);
-                        }
-                        if (fp64)
-                            for (int t = a; t < z; ++t) {
-                                const int j = sh.list[t];
-                                if (j > i) pair_term64(q, sh.pos[j], two_r64, four_r2_64, eoc, etc);
+                        const int mcount = sh.list_n[i];
+                        for (int t = 0; t < mcount; ++t) {
+                            const int j = sh.list[t][i];
+                            const float2 pj = sh.pos[j];
+                            pair_term32(q, pj, j > i, two_r, four_r2, ec, gx, gy);
+                            // FP64 energies only where FP32 sees (nearly) an overlap:
+                            // outside a 1e-5 band the FP64 terms are zero
+                            if (fp64 && j > i) {
+                                const float dx = q.x - pj.x, dy = q.y - pj.y;
+                                if (dx * dx + dy * dy < four_r2_band)
+                                    pair_term64(q, pj, two_r64, four_r2_64, eoc, etc);
                             }
+                        }
                     } else {
                         // list overflow: every circle of the 3 x 3 cells
                         const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
@@ -501,7 +487,11 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                 if (j == i) continue;
                                 const float2 pj = sh.pos[j];
                                 pair_term32(q, pj, j > i, two_r, four_r2, ec, gx, gy);
-                                if (fp64 && j > i) pair_term64(q, pj, two_r64, four_r2_64, eoc, etc);
+                                if (fp64 && j > i) {
+                                    const float dx = q.x - pj.x, dy = q.y - pj.y;
+                                    if (dx * dx + dy * dy < four_r2_band)
+                                        pair_term64(q, pj, two_r64, four_r2_64, eoc, etc);
+                                }
                             }
                         }
                     }
@@ -694,6 +684,19 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         }
 
         // ---- write back ------------------------------------------------------
+        {
+            // listed pairs i<j summed over evaluations (each pair once: by the
+            // thread of its lower index)
+            unsigned long long pm = (unsigned long long)pair_mine;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) pm += __shfl_xor(pm, o, kWave);
+            __syncthreads();
+            if (lane == 0) sh.red64[0][wv][0] = __builtin_bit_cast(double, pm);
+            __syncthreads();
+            pm = 0;
+            for (int w = 0; w < kDW; ++w) pm += __builtin_bit_cast(unsigned long long, sh.red64[0][w][0]);
+            pair_mine = (int64_t)pm;
+        }
 #pragma unroll
         for (int c = 0; c < kCPT; ++c)
             if (act[c]) reinterpret_cast<float2 *>(xy)[off + tid + c * kDB] = x[c];
@@ -703,7 +706,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             r.iters = it;
             r.evals = evals;
             r.rebuilds = rebuilds;
-            r.pair_evals = pair_evals;
+            r.pair_evals = pair_mine;
             r.E32 = E;
             r.gnorm = sqrtf(fmaxf(sh.Bm[cur][kG * kNB + kG], 0.f));
             r.E64 = fp64 ? E64t : -1.0;

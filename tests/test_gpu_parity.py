@@ -40,8 +40,18 @@ def mixed_batch(seed=0, sizes=(0, 1, 2, 17, 64, 333, 700, 1000, 1024, 513)):
     return synth.pack(xys, Rs)
 
 
+def crowded_batch():
+    # 35 circles inside a disk of radius 0.6: each has more than 24
+    # neighbors within the cutoff, which the descent's list cannot hold
+    rng = synth.rng_for(8)
+    core = synth.disk_uniform(35, 1.6, rng)
+    rest = synth.disk_uniform(25, 8.0, rng)
+    return synth.pack([np.concatenate([core, rest])], [8.0])
+
+
 BATCHES = {
     "C1": lambda: synth.C1(),
+    "crowded": crowded_batch,
     "C2": lambda: synth.C2(1),
     "mixed": lambda: mixed_batch(0),
     "C3starts": lambda: synth.C3(24),
@@ -224,7 +234,7 @@ def run_gpu(P, inst, params):
     return xy.cpu().numpy().reshape(-1, 2), res
 
 
-@pytest.mark.parametrize("name", ["C1", "C2", "mixed"])
+@pytest.mark.parametrize("name", ["C1", "C2", "mixed", "crowded"])
 @pytest.mark.parametrize("iters", [1, 2, 3, 6])
 def test_descent_first_iterations_follow_oracle(P, name, iters):
     inst = BATCHES[name]()
