@@ -4,7 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
-#include "../../include/pecc.h"
+#include "pecc.h"
 #include "pecc_launch.hpp"
 
 namespace {

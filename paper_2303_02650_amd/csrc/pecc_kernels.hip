@@ -188,10 +188,15 @@ __global__ __launch_bounds__(kBuildBlock) void build_fill_kernel(
 // ---------------------------------------------------------------------------
 // Energy and gradient over a full CSR list (Def. 3.1, Def. 3.2).  Each
 // thread owns circles and sums their pair terms in list order: no atomics.
-// The instance's list segment is staged in LDS when it fits.
+// One workgroup of 512 threads per instance; positions (8 KB) and the
+// instance's list segment (when it fits, 24 KB) are staged in LDS with
+// coalesced streaming (non-temporal) loads, so global memory sees each byte
+// once, and the gradient leaves with streaming stores.  Four workgroups
+// (32 waves) stay resident per CU, overlapping one instance's loads with
+// another's arithmetic.
 // ---------------------------------------------------------------------------
-constexpr int kSweepBlock = 256;
-constexpr int kColLds = 8192;
+constexpr int kSweepBlock = 512;
+constexpr int kColLds = 6144;
 
 __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ R,
@@ -218,9 +223,24 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         return;
     }
     const bool staged = len <= kColLds;
-    stage_positions<kSweepBlock>(xy, off, n, pos);
-    if (staged)
-        for (int k = threadIdx.x; k < len; k += kSweepBlock) col_s[k] = col[r0 + k];
+    // positions: float4 loads where the instance start is 16-byte aligned
+    if ((reinterpret_cast<uintptr_t>(xy + 2 * (int64_t)off) & 15) == 0) {
+        const float4 *src = reinterpret_cast<const float4 *>(xy + 2 * (int64_t)off);
+        float4 *dst = reinterpret_cast<float4 *>(pos);
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        for (int k = threadIdx.x; k < n / 2; k += kSweepBlock) {
+            const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(&src[k]));
+            dst[k] = make_float4(t.x, t.y, t.z, t.w);
+        }
+        if ((n & 1) && threadIdx.x == 0) pos[n - 1] = reinterpret_cast<const float2 *>(xy)[off + n - 1];
+    } else {
+        stage_positions<kSweepBlock>(xy, off, n, pos);
+    }
+    if (staged) {
+#pragma unroll 4
+        for (int k = threadIdx.x; k < len; k += kSweepBlock)
+            col_s[k] = __builtin_nontemporal_load(&col[r0 + k]);
+    }
     __syncthreads();
     const float Rb = R[b];
     const float two_r = 2.0f * rad, four_r2 = two_r * two_r;
@@ -230,37 +250,36 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         int a = row[off + i] - r0, z = row[off + i + 1] - r0;
         a = a < 0 ? 0 : a;
         z = z > len ? len : z;
-        float gx = 0.0f, gy = 0.0f;
+        float gx = 0.0f, gy = 0.0f, ei = 0.0f;
         for (int k = a; k < z; ++k) {
             const int j = (staged ? col_s[k] : col[r0 + k]) - off;
             if ((unsigned)j >= (unsigned)n) continue;   // entry outside the instance
             const float2 pj = pos[j];
             const float dx = pi.x - pj.x, dy = pi.y - pj.y;
             const float l2 = dx * dx + dy * dy;
-            if (l2 < four_r2) {
-                const float l = sqrtf(l2);
-                const float d = two_r - l;
-                if (j > i) e += d * d;
-                if (l > 0.0f) {
-                    const float kf = -2.0f * d / l;
-                    gx += kf * dx;
-                    gy += kf * dy;
-                }
-            }
+            // branch-free: d = 0 without overlap, no gradient at l = 0
+            const bool ov = l2 < four_r2;
+            const float il = (ov && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
+            const float d = ov ? two_r - l2 * il : 0.f;
+            ei += j > i ? d * d : 0.f;
+            const float kf = -2.f * d * il;
+            gx += kf * dx;
+            gy += kf * dy;
         }
-        const float rho = sqrtf(pi.x * pi.x + pi.y * pi.y);
-        const float d0 = rho + rad - Rb;
-        if (d0 > 0.0f) {
-            e += d0 * d0;
-            if (rho > 0.0f) {
-                const float kc = 2.0f * d0 / rho;
-                gx += kc * pi.x;
-                gy += kc * pi.y;
-            }
-        }
+        const float r2 = pi.x * pi.x + pi.y * pi.y;
+        const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+        const float d0 = fmaxf(r2 * ir + rad - Rb, 0.f);
+        ei += d0 * d0;
+        const float kc = 2.f * d0 * ir;
+        gx += kc * pi.x;
+        gy += kc * pi.y;
         // E sums over every circle: a non-finite position makes it NaN
-        if (!(isfinite(pi.x) && isfinite(pi.y))) e = __builtin_nanf("");
-        if (grad) reinterpret_cast<float2 *>(grad)[off + i] = make_float2(gx, gy);
+        if (!(isfinite(pi.x) && isfinite(pi.y))) ei = __builtin_nanf("");
+        e += ei;
+        if (grad) {
+            __builtin_nontemporal_store(gx, &grad[2 * (int64_t)(off + i)]);
+            __builtin_nontemporal_store(gy, &grad[2 * (int64_t)(off + i) + 1]);
+        }
     }
     const float tot = block_sum<kSweepBlock>(e, sum_tmp);
     if (threadIdx.x == 0) energy[b] = tot;
