@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep roofline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance path")
+    ap.add_argument("--no-restarts", action="store_true", help="skip the batched restart workload")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
     return ap.parse_args()
@@ -228,6 +229,46 @@ def main():
         line["batched_over_plain"] = value / plain_rate
         line["plain_sample"] = k
         print(f"[bench] plain: {k} descents in {plain_wall:.3f} s", file=sys.stderr, flush=True)
+
+    # ---- batched restarts: 256 converged packings, 5% relocated ------------
+    if not a.no_restarts:
+        rs = synth.C3_restarts()
+        dr = P.DeviceInstances.from_host(rs.offset, rs.R)
+        r0 = torch.from_numpy(rs.xy.reshape(-1)).to(dev)
+        rx = torch.empty_like(r0)
+        rws = torch.empty(P.pecc_lbfgs_descend_workspace_size(dr), dtype=torch.uint8, device=dev)
+        rout = torch.empty(dr.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        rf = torch.empty(dr.B, dtype=torch.int32, device=dev)
+        re64 = torch.empty(dr.B, dtype=torch.float64, device=dev)
+
+        def restart_once():
+            rx.copy_(r0)
+            P.pecc_lbfgs_descend(dr, rx, Pc, rout, rws)
+            P.pecc_verify(dr, rx, 1e-20, re64, None, None, rf)
+
+        restart_once()
+        torch.cuda.synchronize()
+        g_rs = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g_rs, stream=side):
+                restart_once()
+        torch.cuda.synchronize()
+        g_rs.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            g_rs.replay()
+        torch.cuda.synchronize()
+        rms = (time.perf_counter() - t0) * 1e3 / a.steps
+        rr = P.results(rout)
+        line["restarts"] = {
+            "workload": f"{dr.B} restarts, n in [300,1000], R = sqrt(n/0.84), 5% relocated",
+            "descents_per_s": dr.B / (rms / 1e3), "ms_per_step": rms,
+            "pair_evals_per_s": float(rr["pair_evals"].sum()) / (rms / 1e3),
+            "feasible_fraction": float(rf.cpu().numpy().mean()),
+            "status_counts": {P.STATUS[s]: int((rr["status"] == s).sum()) for s in np.unique(rr["status"])},
+            "iters_mean": float(rr["iters"].mean()), "iters_max": int(rr["iters"].max())}
+        print(f"[bench] restarts: {rms:.2f} ms/step", file=sys.stderr, flush=True)
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:

@@ -126,7 +126,9 @@ int pecc_energy_grad(const pecc_instances *inst, const float *xy,
  * Eq. 9), run for every instance of the batch in ONE persistent launch.
  * Each workgroup takes instances from a queue (largest n first), keeps the
  * instance's positions, neighbor list and curvature history on chip and
- * iterates until a stop test holds.  xy is updated in place.
+ * iterates until a stop test holds.  xy is updated in place.  The FP32
+ * arithmetic uses R; the FP64 decisions (FEASIBLE, the near-zero
+ * sufficient-decrease test) use R64 when it is given, like pecc_verify.
  * ------------------------------------------------------------------------ */
 typedef struct pecc_descent_params {
     int32_t m;              /* L-BFGS memory, 1..PECC_MAX_M (10)               */

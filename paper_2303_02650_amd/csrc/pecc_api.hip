@@ -183,7 +183,7 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent
     a.e_feasible = p->e_feasible;
     a.tau64 = p->tau64;
     const int grid = pecc::descend_grid(inst->num_instances);
-    return check_hip(pecc::launch_descend(inst->offset, inst->R, xy, inst->num_instances,
+    return check_hip(pecc::launch_descend(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
                                           inst->total_n, a, out, (int32_t *)workspace, grid,
                                           stream),
                      fn);

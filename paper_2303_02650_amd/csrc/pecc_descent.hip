@@ -43,8 +43,9 @@ constexpr int sScYc = sGG + 2;                              // sc . yc
 constexpr int sYcYc = sGG + 3;                              // yc . yc
 constexpr int sScG = sGG + 4;                               // sc . gt
 constexpr int sYcG = sGG + 5;                               // yc . gt
-constexpr int sE = sGG + 6;                                 // trial energy
-static_assert(sE < kWave, "fused reduction must fit one slot per lane");
+constexpr int sE = sGG + 6;                                 // trial energy (radius rad)
+constexpr int sE1 = sGG + 7;                                // trial energy of unit circles
+static_assert(sE1 < kWave, "fused reduction must fit one slot per lane");
 
 struct DescentShared {
     float2 pos[kMaxN];
@@ -79,10 +80,10 @@ __device__ __forceinline__ float dot2(float2 a, float2 b) { return a.x * b.x + a
 __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[kCPT], const float2 (&sc)[kCPT],
                                             const float2 (&yc)[kCPT],
                                             const float2 (&S)[kMM][kCPT],
-                                            const float2 (&Y)[kMM][kCPT], float e)
+                                            const float2 (&Y)[kMM][kCPT], float e, float e1)
 {
     if (v == sE) return e;
-    if (v > sE) return 0.0f;
+    if (v == sE1) return e1;
     float acc = 0.0f;
 #pragma unroll
     for (int c = 0; c < kCPT; ++c) {
@@ -165,7 +166,8 @@ __device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[kCPT],
                                                      const float2 (&sc)[kCPT],
                                                      const float2 (&yc)[kCPT],
                                                      const float2 (&S)[kMM][kCPT],
-                                                     const float2 (&Y)[kMM][kCPT], float e)
+                                                     const float2 (&Y)[kMM][kCPT], float e,
+                                                     float e1)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
@@ -176,8 +178,8 @@ __device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[kCPT],
         float t1[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float lo = slot_value(u + 8 * k, gt, sc, yc, S, Y, e);
-            const float hi = slot_value(u + 8 * k + 32, gt, sc, yc, S, Y, e);
+            const float lo = slot_value(u + 8 * k, gt, sc, yc, S, Y, e, e1);
+            const float hi = slot_value(u + 8 * k + 32, gt, sc, yc, S, Y, e, e1);
             t1[k] = (b3 ? hi : lo) + dpp<kDppRowMirror>(b3 ? lo : hi);
         }
         float t2[2];
@@ -270,14 +272,19 @@ __device__ __forceinline__ bool near_cut(float2 a, float2 b, float c2lo, float c
 // gradient.  (With branches the compiler merges the accumulations into one
 // store through a selected address and moves the accumulators to memory.)
 __device__ __forceinline__ void pair_term32(float2 q, float2 pj, bool count_e, float two_r,
-                                            float four_r2, float &e, float &gx, float &gy)
+                                            float four_r2, float &e, float &e1, float &gx,
+                                            float &gy)
 {
     const float dx = q.x - pj.x, dy = q.y - pj.y;
     const float l2 = dx * dx + dy * dy;
     const bool ov = l2 < four_r2;
     const float il = (ov && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
     const float d = ov ? two_r - l2 * il : 0.f;
+    // the same pair for unit circles (rad <= the descent's radius): overlap
+    // 2 - l, which is d - (two_r - 2) whenever it is positive
+    const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
     e += count_e ? d * d : 0.f;
+    e1 += count_e ? d1 * d1 : 0.f;
     const float kf = -2.f * d * il;
     gx += kf * dx;
     gy += kf * dy;
@@ -302,7 +309,8 @@ __device__ __forceinline__ void pair_term64(float2 q, float2 pj, double two_r64,
 enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2 };
 
 __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
-    const int32_t *__restrict__ offset, const float *__restrict__ Rv, float *__restrict__ xy,
+    const int32_t *__restrict__ offset, const float *__restrict__ Rv,
+    const double *__restrict__ Rv64, float *__restrict__ xy,
     int B, int64_t total_n, DescentArgs A, DescentResultDev *__restrict__ out,
     int32_t *__restrict__ queue)
 {
@@ -338,7 +346,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         const float rad = A.rad, two_r = 2.0f * rad, four_r2 = two_r * two_r;
         const float four_r2_band = four_r2 * (1.0f + 1e-5f);
         const double rad64 = (double)rad, two_r64 = 2.0 * rad64, four_r2_64 = two_r64 * two_r64;
-        const double R64 = (double)R;
+        // FP64 decisions (feasibility, the near-zero line search) use the
+        // caller's FP64 radius when there is one, as pecc_verify does
+        const double R64 = Rv64 ? Rv64[b] : (double)R;
         const Grid grid = make_grid(R, A.h_req);
 
         // ---- per-thread state (circle c of this thread is tid + c*kDB) ----
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) pair_mine += half_mine[c];
             // ---- pair sweep: energy and gradient of this thread's circles ----
-            float e = 0.f;
+            float e = 0.f, e1 = 0.f;
             double eo = 0.0, et = 0.0;
             float2 gt[kCPT], yc[kCPT];
 #pragma unroll
@@ -458,14 +468,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const float2 q = xt[c];
                 float gx = 0.f, gy = 0.f;
                 if (act[c]) {
-                    float ec = 0.f;
+                    float ec = 0.f, e1c = 0.f;
                     double eoc = 0.0, etc = 0.0;
                     if (!overflow) {
                         const int mcount = sh.list_n[i];
                         for (int t = 0; t < mcount; ++t) {
                             const int j = sh.list[t][i];
                             const float2 pj = sh.pos[j];
-                            pair_term32(q, pj, j > i, two_r, four_r2, ec, gx, gy);
+                            pair_term32(q, pj, j > i, two_r, four_r2, ec, e1c, gx, gy);
                             // FP64 energies only where FP32 sees (nearly) an overlap:
                             // outside a 1e-5 band the FP64 terms are zero
                             if (fp64 && j > i) {
@@ -486,7 +496,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                 const int j = sh.cell_circ[t];
                                 if (j == i) continue;
                                 const float2 pj = sh.pos[j];
-                                pair_term32(q, pj, j > i, two_r, four_r2, ec, gx, gy);
+                                pair_term32(q, pj, j > i, two_r, four_r2, ec, e1c, gx, gy);
                                 if (fp64 && j > i) {
                                     const float dx = q.x - pj.x, dy = q.y - pj.y;
                                     if (dx * dx + dy * dy < four_r2_band)
@@ -496,6 +506,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         }
                     }
                     e += ec;
+                    e1 += e1c;
                     eo += eoc;
                     et += etc;
                     // containment (branch-free, as the pair term)
@@ -503,6 +514,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
                     const float d0 = fmaxf(r2 * ir + rad - R, 0.f);
                     e += d0 * d0;
+                    const float d01 = fmaxf(d0 - (rad - 1.f), 0.f);
+                    e1 += d01 * d01;
                     const float kc = 2.f * d0 * ir;
                     gx += kc * q.x;
                     gy += kc * q.y;
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     // E sums over every circle: a non-finite position makes it NaN
                     if (!(isfinite(q.x) && isfinite(q.y))) {
-                        e = __builtin_nanf("");
+                        e = e1 = __builtin_nanf("");
                         eo = et = __builtin_nan("");
                     }
                 }
@@ -523,7 +536,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 yc[c] = make_float2(gx - g[c].x, gy - g[c].y);
             }
             // ---- fused reduction: 63 dot products and E in one pass ----------
-            const float wsum = wave_reduce_scatter(gt, sc, yc, S, Y, e);
+            const float wsum = wave_reduce_scatter(gt, sc, yc, S, Y, e, e1);
             sh.red[par][wv][lane_slot(lane)] = wsum;
             if (fp64) {
                 const double wo = wave_sum(eo), wt = wave_sum(et);
@@ -539,6 +552,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 for (int w = 0; w < kDW; ++w) { so += sh.red64[par][w][0]; st += sh.red64[par][w][1]; }
             }
             const float Et = lane_value(tot, sE);
+            const float E1t = lane_value(tot, sE1);
 
             // ================= what the evaluation was for =====================
             bool accept = false, push = false;
@@ -596,7 +610,10 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (req == kReqTrial) ++it;
                 E = Et;
                 if (fp64) { E64o = so; E64t = st; }
-                if (!fp64 && A.tau64 > 0.0 && (double)E < A.tau64) {
+                // FP64 regime once either FP32 energy is small: with a contact
+                // margin the unit circles can be overlap-free while E (radius
+                // rad) still sums (2 mu)^2 over every contact
+                if (!fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
                     fp64 = true;
                     req = kReqFp64;          // FP64 energies of x before going on
                     continue;
@@ -765,13 +782,13 @@ int descend_grid(int B)
     return B < cap ? B : cap;
 }
 
-hipError_t launch_descend(const int32_t *offset, const float *R, float *xy, int B,
-                          int64_t total_n, const DescentArgs &a, void *out, int32_t *queue,
-                          int grid, hipStream_t s)
+hipError_t launch_descend(const int32_t *offset, const float *R, const double *R64, float *xy,
+                          int B, int64_t total_n, const DescentArgs &a, void *out,
+                          int32_t *queue, int grid, hipStream_t s)
 {
     queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
     if (grid < 1) grid = 1;
-    lbfgs_descend_kernel<<<grid, kDB, 0, s>>>(offset, R, xy, B, total_n, a,
+    lbfgs_descend_kernel<<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
                                               reinterpret_cast<DescentResultDev *>(out), queue);
     return hipGetLastError();
 }

@@ -28,8 +28,8 @@ struct DescentArgs {
 
 struct DescentResultDev;  // layout-identical to pecc_descent_result
 
-hipError_t launch_descend(const int32_t *offset, const float *R, float *xy, int B,
-                          int64_t total_n, const DescentArgs &a, void *out,
+hipError_t launch_descend(const int32_t *offset, const float *R, const double *R64, float *xy,
+                          int B, int64_t total_n, const DescentArgs &a, void *out,
                           int32_t *queue, int grid, hipStream_t s);
 
 int descend_grid(int B);   // persistent workgroups to launch for B instances

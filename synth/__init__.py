@@ -162,3 +162,15 @@ def C4(count: int = 64) -> Instances:
 def C5(count: int = 128) -> Instances:
     """n = 1000, R = 34.4 (learned-proposal evaluation shape), seed 5."""
     return instance_set(count, 1000, 34.4, seed=5)
+
+
+def C3_restarts(path: str | None = None) -> Instances:
+    """The batched restart workload: 256 oracle-converged C3 packings with
+    5% of their circles relocated (tests/golden/c3_restarts.npz, written by
+    tests/golden/make_c3_restarts.py)."""
+    import os
+    p = path or os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "tests", "golden", "c3_restarts.npz")
+    z = np.load(p, allow_pickle=False)
+    return Instances(xy=np.ascontiguousarray(z["xy"]), offset=z["offset"].astype(np.int32),
+                     R=z["R"].astype(np.float64))

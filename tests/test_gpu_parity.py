@@ -56,6 +56,7 @@ BATCHES = {
     "mixed": lambda: mixed_batch(0),
     "C3starts": lambda: synth.C3(24),
     "C4x8": lambda: synth.C4(8),
+    "C3restarts": lambda: synth.C3_restarts(),
 }
 
 
@@ -234,7 +235,16 @@ def run_gpu(P, inst, params):
     return xy.cpu().numpy().reshape(-1, 2), res
 
 
-@pytest.mark.parametrize("name", ["C1", "C2", "mixed", "crowded"])
+def c3_subset():
+    full = synth.C3_restarts()
+    pick = [0, 17, 101, 255]
+    return synth.pack([full.instance(b) for b in pick], full.R[pick])
+
+
+BATCHES["C3sub"] = c3_subset
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "mixed", "crowded", "C3sub"])
 @pytest.mark.parametrize("iters", [1, 2, 3, 6])
 def test_descent_first_iterations_follow_oracle(P, name, iters):
     inst = BATCHES[name]()
@@ -364,3 +374,17 @@ def test_nonfinite_positions_give_nan_everywhere(P):
     assert np.isnan(E[0].item()) and np.isfinite(E[1].item())
     assert np.isnan(e[0]) and np.isnan(mp[0]) and np.isnan(mc[0]) and f[0] == 0
     assert np.isfinite(e[1])
+
+
+def test_c3_restart_batch_descends(P):
+    inst = synth.C3_restarts()
+    xg, res = run_gpu(P, inst, P.DescentParams(max_iter=5000, contact_margin=1e-4))
+    assert set(np.unique(res["status"])) <= {1, 2, 3, 4, 5}
+    d, xy = to_dev(P, inst)
+    xy.copy_(torch.from_numpy(xg.reshape(-1)))
+    e64, _, _, f = [t.cpu().numpy() for t in P.verify(d, xy)]
+    # every FEASIBLE claim is confirmed by the FP64 oracle on a sample
+    for b in np.flatnonzero(res["status"] == 1)[:8]:
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        assert oracle.verify(xg[o0:o1], inst.R[b])["feasible"]
+    assert (f == (res["status"] == 1)).all()
