@@ -13,6 +13,7 @@ arrays through ctypes.  Each function names the part of the paper it follows:
   neighbors          Gamma(i) of Sec. 4.3, FP64 predicate on FP32 inputs
   two_loop           H g for the inverse update of Eq. 10-11 (limited memory)
   descend            Alg. 1 with one batch, L-BFGS reading of Eq. 8-11
+  gbo_descend        Alg. 1 with geometric batches (2D grid blocks, 4 colours)
   verify             Eq. 1-2 checked through E (Eq. 5) in FP64
 """
 from __future__ import annotations
@@ -65,6 +66,11 @@ def lib():
         L.oracle_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_void_p, dp]
         L.oracle_verify.restype = C.c_int
         L.oracle_verify.argtypes = [C.c_int, fp, C.c_double, C.c_double, dp]
+        L.oracle_gbo_batches.restype = C.c_int
+        L.oracle_gbo_batches.argtypes = [C.c_int, dp, C.c_double, C.c_int, ip, ip]
+        L.oracle_gbo_descend.restype = C.c_int
+        L.oracle_gbo_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, dp]
         _lib = L
     return _lib
 
@@ -186,3 +192,47 @@ def verify(xy32, R: float, tol: float = 1e-20):
                             out.ctypes.data_as(C.POINTER(C.c_double)))
     return {"E": out[0], "max_pair_overlap": out[1], "max_cont_overlap": out[2],
             "feasible": bool(f)}
+
+
+class _GboParams(C.Structure):
+    _fields_ = [("blocks", C.c_int32), ("max_outer", C.c_int32), ("jacobi", C.c_int32),
+                ("pad", C.c_int32), ("skin_half", C.c_double)]
+
+
+class _GboResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("visits", C.c_int32),
+                ("evals", C.c_int32), ("stalled_visits", C.c_int32), ("ref_resets", C.c_int32),
+                ("E", C.c_double), ("gsum", C.c_double)]
+
+
+def gbo_batches(xy, R: float, blocks: int):
+    """Batch id and colour of every circle for a blocks x blocks grid."""
+    xy, px = _d(np.asarray(xy).reshape(-1, 2))
+    b = np.zeros(xy.shape[0], dtype=np.int32)
+    c = np.zeros(xy.shape[0], dtype=np.int32)
+    lib().oracle_gbo_batches(xy.shape[0], px, float(R), int(blocks),
+                             b.ctypes.data_as(C.POINTER(C.c_int32)),
+                             c.ctypes.data_as(C.POINTER(C.c_int32)))
+    return b, c
+
+
+def gbo_descend(xy, R: float, params: DescentParams | None = None, blocks: int = 4,
+                max_outer: int = 5000, jacobi: bool = True, skin_half: float = 0.15,
+                trace: bool = False):
+    """Geometric batch descent in FP64.  Returns (xy_final, result, trace)."""
+    P = params or DescentParams()
+    x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
+    cp = _Params(**asdict(P))
+    gp = _GboParams(int(blocks), int(max_outer), 1 if jacobi else 0, 0, float(skin_half))
+    cr = _GboResult()
+    tr = np.zeros(max_outer + 1, dtype=np.float64) if trace else None
+    rc = lib().oracle_gbo_descend(x.shape[0], px, float(R), C.byref(cp), C.byref(gp), C.byref(cr),
+                                  tr.ctypes.data_as(C.POINTER(C.c_double)) if trace else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle_gbo_descend failed ({rc})")
+    res = {"status": STATUS[cr.status], "outer": cr.outer, "visits": cr.visits,
+           "evals": cr.evals, "stalled_visits": cr.stalled_visits,
+           "ref_resets": cr.ref_resets, "E": cr.E, "gsum": cr.gsum}
+    if trace:
+        tr = tr[:cr.outer + 1]
+    return x, res, tr

@@ -432,3 +432,249 @@ int oracle_verify(int n, const float *xy, double R, double tol, double *out)
     out[2] = mc;
     return (sp + sc) < tol ? 1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Geometric batch descent (Alg. 1) with the limited-memory reading of      */
+/* Eq. 8-11, the batch energy of Eq. 7 and a 2D grid-block partition.       */
+/*                                                                           */
+/* Partition (Alg. 1 line 1), fixed for the whole descent: block side        */
+/* S = 2R / blocks over [-R, R]^2; circle i goes to block (bx, by) with      */
+/* bx = clamp(floor((x_i + R) / S), 0, blocks-1) (likewise by), batch id     */
+/* p = by * blocks + bx, colour (bx mod 2) + 2 (by mod 2).  Batches are       */
+/* visited colour by colour (0..3), in increasing p inside a colour.  With   */
+/* jacobi = 1 every batch of a colour sees the others' positions as they     */
+/* were when the colour started (the GPU runs them concurrently); with       */
+/* jacobi = 0 it sees the latest ones (sequential order).                    */
+/*                                                                           */
+/* A visit is one quasi-Newton iteration on E(x_p) (Eq. 7) with the other   */
+/* circles fixed: gradient, direction from the batch's own (s, y) history,  */
+/* backtracking sufficient decrease, curvature pair under the same fixed     */
+/* environment.  skin_half > 0 caps every trial: a step that would move a    */
+/* circle more than skin_half away from its reference position is halved     */
+/* (counted as a halving); after each colour the references are reset to     */
+/* the current positions once some circle has moved more than skin_half/2   */
+/* (the GPU rebuilds its neighbor lists at that point).  A visit whose line  */
+/* search fails leaves the batch unchanged.                                  */
+/*                                                                           */
+/* Outer iteration (Alg. 1 lines 5-16) stop tests, at its top: non-finite   */
+/* E, E < e_feasible, sum over batches of ||g(x_p)||_2 of the previous outer */
+/* iteration <= g_tol, relative decrease of E over ftol_window outer        */
+/* iterations <= ftol, max_outer reached.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t blocks;
+    int32_t max_outer;
+    int32_t jacobi;
+    int32_t pad;
+    double skin_half;
+} oracle_gbo_params;
+
+typedef struct {
+    int32_t status;
+    int32_t outer;
+    int32_t visits;
+    int32_t evals;
+    int32_t stalled_visits;
+    int32_t ref_resets;
+    double E;
+    double gsum;
+} oracle_gbo_result;
+
+int oracle_gbo_batches(int n, const double *xy, double R, int blocks, int32_t *batch_of,
+                       int32_t *colour_of)
+{
+    const double S = 2.0 * R / blocks;
+    for (int i = 0; i < n; ++i) {
+        double tx = floor((xy[2 * i] + R) / S), ty = floor((xy[2 * i + 1] + R) / S);
+        int bx = tx < 0 ? 0 : (tx > blocks - 1 ? blocks - 1 : (int)tx);
+        int by = ty < 0 ? 0 : (ty > blocks - 1 ? blocks - 1 : (int)ty);
+        if (tx != tx) bx = 0;
+        if (ty != ty) by = 0;
+        batch_of[i] = by * blocks + bx;
+        colour_of[i] = (bx & 1) + 2 * (by & 1);
+    }
+    return blocks * blocks;
+}
+
+int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
+                       const oracle_gbo_params *G, oracle_gbo_result *res, double *trace)
+{
+    const int nb = G->blocks * G->blocks, m = P->m;
+    if (G->blocks < 1 || m < 1 || m > 64) return -2;
+    int32_t *batch_of = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *colour_of = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    int32_t *mask = calloc(n > 0 ? n : 1, sizeof(int32_t));
+    int *cnt = calloc(nb, sizeof(int)), *start = calloc(nb + 1, sizeof(int));
+    int *member = malloc(sizeof(int) * (n > 0 ? n : 1));
+    int *kh = calloc(nb, sizeof(int));
+    double **Sh = calloc(nb, sizeof(double *)), **Yh = calloc(nb, sizeof(double *));
+    double *snap = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *env = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *nx = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *xref = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *g = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *gt = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *bg = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *bp = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *bs = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *by = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    double *bx0 = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    const int W = P->ftol_window > 0 ? P->ftol_window : 1;
+    double *ehist = calloc(W + 1, sizeof(double));
+    int rc = 0;
+    if (!batch_of || !colour_of || !mask || !cnt || !start || !member || !kh || !Sh || !Yh ||
+        !snap || !env || !nx || !xref || !g || !gt || !bg || !bp || !bs || !by || !bx0 || !ehist) {
+        rc = -1;
+        goto done;
+    }
+    oracle_gbo_batches(n, xy, R, G->blocks, batch_of, colour_of);
+    for (int i = 0; i < n; ++i) ++cnt[batch_of[i]];
+    for (int p = 0; p < nb; ++p) start[p + 1] = start[p] + cnt[p];
+    {
+        int *fill = calloc(nb, sizeof(int));
+        if (!fill) { rc = -1; goto done; }
+        for (int i = 0; i < n; ++i) member[start[batch_of[i]] + fill[batch_of[i]]++] = i;
+        free(fill);
+    }
+    for (int p = 0; p < nb; ++p) {
+        const int dim = 2 * cnt[p];
+        Sh[p] = calloc((size_t)m * (dim > 0 ? dim : 1), sizeof(double));
+        Yh[p] = calloc((size_t)m * (dim > 0 ? dim : 1), sizeof(double));
+        if (!Sh[p] || !Yh[p]) { rc = -1; goto done; }
+    }
+    memcpy(xref, xy, sizeof(double) * 2 * n);
+    int visits = 0, evals = 0, stalled = 0, resets = 0, t = 0, status = OR_RUNNING;
+    double E = oracle_energy_grad(n, xy, R, P->rad, NULL, NULL, NULL);
+    double gsum_prev = -1.0, gsum = 0.0;
+    const double cap2 = G->skin_half * G->skin_half;
+    for (t = 0;; ++t) {
+        if (trace) trace[t] = E;
+        if (!isfinite(E)) { status = OR_NONFINITE; break; }
+        if (E < P->e_feasible) { status = OR_FEASIBLE; break; }
+        if (t > 0 && gsum_prev <= P->g_tol) { status = OR_STATIONARY; break; }
+        if (P->ftol > 0.0 && t >= W) {
+            const double e_old = ehist[(t - W) % (W + 1)];
+            if (e_old - E <= P->ftol * e_old) { status = OR_CONVERGED; break; }
+        }
+        ehist[t % (W + 1)] = E;
+        if (t >= G->max_outer) { status = OR_MAX_ITER; break; }
+        gsum = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            memcpy(snap, xy, sizeof(double) * 2 * n);
+            memcpy(nx, xy, sizeof(double) * 2 * n);
+            for (int p = 0; p < nb; ++p) {
+                const int np = cnt[p];
+                if (np == 0) continue;
+                const int *mem = member + start[p];
+                if (colour_of[mem[0]] != c) continue;
+                const int dim = 2 * np;
+                ++visits;
+                /* environment: other circles at the colour's start (jacobi) or now */
+                memcpy(env, G->jacobi ? snap : nx, sizeof(double) * 2 * n);
+                for (int q = 0; q < np; ++q) {
+                    env[2 * mem[q]] = xy[2 * mem[q]];
+                    env[2 * mem[q] + 1] = xy[2 * mem[q] + 1];
+                    mask[mem[q]] = 1;
+                }
+                const double Ep = oracle_batch_energy_grad(n, env, R, P->rad, mask, g);
+                ++evals;
+                double gn2 = 0.0;
+                for (int q = 0; q < np; ++q) {
+                    bg[2 * q] = g[2 * mem[q]];
+                    bg[2 * q + 1] = g[2 * mem[q] + 1];
+                    bx0[2 * q] = env[2 * mem[q]];
+                    bx0[2 * q + 1] = env[2 * mem[q] + 1];
+                }
+                for (int d = 0; d < dim; ++d) gn2 += bg[d] * bg[d];
+                const double gn = sqrt(gn2);
+                gsum += gn;
+                oracle_two_loop(dim, kh[p], Sh[p], Yh[p], bg, bp);
+                for (int d = 0; d < dim; ++d) bp[d] = -bp[d];
+                double gp = dot(dim, bg, bp);
+                if (kh[p] > 0 && !(gp < 0.0)) {
+                    kh[p] = 0;
+                    for (int d = 0; d < dim; ++d) bp[d] = -bg[d];
+                    gp = dot(dim, bg, bp);
+                }
+                double alpha = kh[p] > 0 ? 1.0 : 1.0 / (gn > 1.0 ? gn : 1.0);
+                int accepted = 0;
+                double Et = 0.0;
+                for (int h = 0; h <= P->max_halvings; ++h) {
+                    int capped = 0;
+                    for (int q = 0; q < np; ++q) {
+                        const double tx = bx0[2 * q] + alpha * bp[2 * q];
+                        const double ty = bx0[2 * q + 1] + alpha * bp[2 * q + 1];
+                        env[2 * mem[q]] = tx;
+                        env[2 * mem[q] + 1] = ty;
+                        if (G->skin_half > 0.0) {
+                            const double dx = tx - xref[2 * mem[q]], dy = ty - xref[2 * mem[q] + 1];
+                            if (dx * dx + dy * dy > cap2) capped = 1;
+                        }
+                    }
+                    if (capped) { alpha *= 0.5; continue; }
+                    Et = oracle_batch_energy_grad(n, env, R, P->rad, mask, gt);
+                    ++evals;
+                    if (Et <= Ep + P->c1 * alpha * gp) { accepted = 1; break; }
+                    alpha *= 0.5;
+                }
+                if (accepted) {
+                    double sy = 0.0, yy = 0.0;
+                    for (int q = 0; q < np; ++q) {
+                        for (int k = 0; k < 2; ++k) {
+                            const int d = 2 * q + k;
+                            bs[d] = env[2 * mem[q] + k] - bx0[d];
+                            by[d] = gt[2 * mem[q] + k] - bg[d];
+                            sy += bs[d] * by[d];
+                            yy += by[d] * by[d];
+                        }
+                    }
+                    if (sy > P->eps_curv * yy) {
+                        if (kh[p] == m) {
+                            memmove(Sh[p], Sh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
+                            memmove(Yh[p], Yh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
+                            kh[p] = m - 1;
+                        }
+                        memcpy(Sh[p] + (size_t)kh[p] * dim, bs, sizeof(double) * dim);
+                        memcpy(Yh[p] + (size_t)kh[p] * dim, by, sizeof(double) * dim);
+                        ++kh[p];
+                    }
+                    for (int q = 0; q < np; ++q) {
+                        nx[2 * mem[q]] = env[2 * mem[q]];
+                        nx[2 * mem[q] + 1] = env[2 * mem[q] + 1];
+                    }
+                } else {
+                    ++stalled;
+                }
+                for (int q = 0; q < np; ++q) mask[mem[q]] = 0;
+                if (!G->jacobi) memcpy(xy, nx, sizeof(double) * 2 * n);
+            }
+            memcpy(xy, nx, sizeof(double) * 2 * n);
+            if (G->skin_half > 0.0) {
+                double mx = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    const double dx = xy[2 * i] - xref[2 * i], dy = xy[2 * i + 1] - xref[2 * i + 1];
+                    const double d2 = dx * dx + dy * dy;
+                    if (d2 > mx) mx = d2;
+                }
+                if (mx > 0.25 * cap2) { memcpy(xref, xy, sizeof(double) * 2 * n); ++resets; }
+            }
+        }
+        gsum_prev = gsum;
+        E = oracle_energy_grad(n, xy, R, P->rad, NULL, NULL, NULL);
+    }
+    res->status = status;
+    res->outer = t;
+    res->visits = visits;
+    res->evals = evals;
+    res->stalled_visits = stalled;
+    res->ref_resets = resets;
+    res->E = E;
+    res->gsum = gsum_prev;
+done:
+    if (Sh) for (int p = 0; p < nb; ++p) free(Sh[p]);
+    if (Yh) for (int p = 0; p < nb; ++p) free(Yh[p]);
+    free(Sh); free(Yh); free(batch_of); free(colour_of); free(mask); free(cnt); free(start);
+    free(member); free(kh); free(snap); free(env); free(nx); free(xref); free(g); free(gt);
+    free(bg); free(bp); free(bs); free(by); free(bx0); free(ehist);
+    return rc;
+}
