@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true", help="skip the standalone sweep roofline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance path")
     ap.add_argument("--no-restarts", action="store_true", help="skip the batched restart workload")
+    ap.add_argument("--no-gbo", action="store_true", help="skip the geometric batch workload")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
     return ap.parse_args()
@@ -269,6 +270,50 @@ def main():
             "status_counts": {P.STATUS[s]: int((rr["status"] == s).sum()) for s in np.unique(rr["status"])},
             "iters_mean": float(rr["iters"].mean()), "iters_max": int(rr["iters"].max())}
         print(f"[bench] restarts: {rms:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # ---- geometric batch descent: 64 x n=1000, R=34.4, 4 x 4 blocks -------
+    if not a.no_gbo:
+        c4 = synth.C4(64)
+        dg = P.DeviceInstances.from_host(c4.offset, c4.R)
+        g0 = torch.from_numpy(c4.xy.reshape(-1)).to(dev)
+        gx = torch.empty_like(g0)
+        gws = torch.empty(P.pecc_gbo_descend_workspace_size(dg, 4), dtype=torch.uint8, device=dev)
+        gout = torch.empty(dg.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        gf = torch.empty(dg.B, dtype=torch.int32, device=dev)
+        ge = torch.empty(dg.B, dtype=torch.float64, device=dev)
+        gbo = {}
+        for tag, margin, fp64 in (("fp32", 1e-4, 0), ("fp32_margin0", 0.0, 0), ("fp64sweep_margin0", 0.0, 1)):
+            gp = descent_params(P, a.max_iter)
+            gp.contact_margin = margin
+            gpc = gp.c()
+            gx.copy_(g0)
+            P.pecc_gbo_descend(dg, gx, gpc, 4, fp64, gout, gws)      # warm-up
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(max(1, min(a.steps, 3))):
+                gx.copy_(g0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                P.pecc_gbo_descend(dg, gx, gpc, 4, fp64, gout, gws)
+                e1.record(stream)
+                P.pecc_verify(dg, gx, 1e-20, ge, None, None, gf)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            gr = P.results(gout)
+            e64 = ge.cpu().numpy()
+            ent = {"descents_per_s": dg.B / (np.mean(ts) / 1e3), "kernel_ms": float(np.mean(ts)),
+                   "feasible_fraction": float(gf.cpu().numpy().mean()),
+                   "outer_iters_mean": float(gr["iters"].mean()),
+                   "status_counts": {P.STATUS[s]: int((gr["status"] == s).sum()) for s in np.unique(gr["status"])},
+                   "E64_median": float(np.median(e64))}
+            if margin == 0.0:
+                rel = np.abs(gr["E32"].astype(np.float64) - e64) / np.maximum(e64, 1e-300)
+                ent["reported_E_rel_err_vs_fp64_median"] = float(np.median(rel[e64 > 0])) if (e64 > 0).any() else 0.0
+                ent["reported_E_rel_err_vs_fp64_max"] = float(rel[e64 > 0].max()) if (e64 > 0).any() else 0.0
+            gbo[tag] = ent
+            print(f"[bench] gbo {tag}: {np.mean(ts):.1f} ms", file=sys.stderr, flush=True)
+        line["gbo"] = {"workload": "64 random starts, n=1000, R=34.4, 4 x 4 blocks (~64 circles per batch)",
+                       **gbo}
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:

@@ -169,6 +169,36 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy,
                        void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Geometric batch descent (Alg. 1 with the batch energy of Eq. 7 and the
+ * limited-memory reading of Eq. 8-11) for every instance of the batch, one
+ * persistent launch.  The circles are partitioned once, from the input
+ * positions, into the blocks of a blocks x blocks grid over [-R, R]^2
+ * (block side 2R / blocks, computed in FP64); block (bx, by) has colour
+ * (bx mod 2) + 2 (by mod 2).  An outer iteration visits the colours in
+ * turn; every batch of the colour takes one quasi-Newton step on its batch
+ * energy with the other circles at their positions from the start of the
+ * colour.  Each batch keeps its own (s, y) history (memory params->m).
+ * A trial step that would move a circle more than skin_half from the
+ * positions of the last neighbor-list rebuild is halved.
+ * params->max_iter counts outer iterations; result.iters as well,
+ * result.gnorm is the sum over batches of ||g(x_p)||_2 of the last outer
+ * iteration (the stop quantity of Alg. 1), result.E64 the FP64 energy of
+ * unit circles.  Stop tests (FP32 except E64): E64 < e_feasible, that sum
+ * <= g_tol, relative decrease of E over ftol_window outer iterations <=
+ * ftol, max_iter.  tau64 is not used.
+ * sweep_fp64 = 1 evaluates the pair terms and batch energies in FP64 (the
+ * line search then tests FP64 energies; directions stay FP32).
+ * Limits: 1 <= blocks <= 8 and at most 128 circles per block (a larger
+ * block makes that instance report PECC_STATUS_BAD_INSTANCE).
+ * ------------------------------------------------------------------------ */
+int pecc_gbo_descend_workspace_size(const pecc_instances *inst, int32_t blocks,
+                                    size_t *bytes /*host*/);
+int pecc_gbo_descend(const pecc_instances *inst, float *xy,
+                     const pecc_descent_params *params /*host*/, int32_t blocks,
+                     int32_t sweep_fp64, pecc_descent_result *out /*device [B]*/,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * FP64 feasibility check of Eq. 1-2 through the energy of Def. 3.2 with
  * unit circles: every pair i<j of each instance is enumerated (no list),
  * in FP64 on the FP32 positions.  Per instance: energy64 = E,

@@ -68,6 +68,10 @@ _sig = {
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "pecc_verify": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pecc_gbo_descend_workspace_size": (C.c_int, [_P(pecc_instances), C.c_int32, _P(C.c_size_t)]),
+    "pecc_gbo_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
+                                   C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                   C.c_void_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -165,6 +169,19 @@ def pecc_lbfgs_descend(inst, xy, params: pecc_descent_params, out, workspace, st
                                    _stream(stream)))
 
 
+def pecc_gbo_descend_workspace_size(inst: DeviceInstances, blocks: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_gbo_descend_workspace_size(C.byref(inst.c()), int(blocks), C.byref(b)))
+    return b.value
+
+
+def pecc_gbo_descend(inst, xy, params: pecc_descent_params, blocks, sweep_fp64, out, workspace,
+                     stream=None):
+    _check(_lib.pecc_gbo_descend(C.byref(inst.c()), _ptr(xy), C.byref(params), int(blocks),
+                                 int(sweep_fp64), _ptr(out), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def pecc_verify(inst, xy, tol, energy64, max_pair, max_cont, feasible, stream=None):
     _check(_lib.pecc_verify(C.byref(inst.c()), _ptr(xy), float(tol), _ptr(energy64),
                             _ptr(max_pair), _ptr(max_cont), _ptr(feasible), _stream(stream)))
@@ -236,6 +253,21 @@ def lbfgs_descend(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams
         workspace = torch.empty(pecc_lbfgs_descend_workspace_size(inst), dtype=torch.uint8,
                                 device=xy.device)
     pecc_lbfgs_descend(inst, xy, P, out, workspace)
+    return out
+
+
+def gbo_descend(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams | None = None,
+                blocks: int = 4, sweep_fp64: bool = False, workspace: torch.Tensor | None = None,
+                out: torch.Tensor | None = None):
+    """Geometric batch descent of every instance in place; returns the
+    device result buffer (see ``results``)."""
+    P = (params or DescentParams()).c()
+    if out is None:
+        out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=xy.device)
+    if workspace is None:
+        workspace = torch.empty(pecc_gbo_descend_workspace_size(inst, blocks), dtype=torch.uint8,
+                                device=xy.device)
+    pecc_gbo_descend(inst, xy, P, blocks, sweep_fp64, out, workspace)
     return out
 
 

@@ -135,15 +135,11 @@ int pecc_lbfgs_descend_workspace_size(const pecc_instances *inst, size_t *bytes)
     return PECC_OK;
 }
 
-int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
-                       pecc_descent_result *out, void *workspace, size_t workspace_bytes,
-                       hipStream_t stream)
+namespace {
+
+// Validates the descent constants and derives the kernels' form of them.
+int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs *a)
 {
-    const char *fn = "pecc_lbfgs_descend";
-    int rc = check_inst(inst, fn);
-    if (rc) return rc;
-    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
-    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
     if (p->m < 1 || p->m > PECC_MAX_M) return fail(PECC_ERR_INVALID, "%s: m = %d outside [1, %d]", fn, p->m, PECC_MAX_M);
     if (p->max_iter < 0) return fail(PECC_ERR_INVALID, "%s: max_iter < 0", fn);
     if (p->max_halvings < 0 || p->max_halvings > 200) return fail(PECC_ERR_INVALID, "%s: max_halvings outside [0, 200]", fn);
@@ -161,31 +157,82 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent
         return fail(PECC_ERR_INVALID, "%s: cutoff %g must exceed 2*(1+contact_margin)", fn, p->cutoff);
     if (p->cell_size > 0.f && p->cell_size < p->cutoff)
         return fail(PECC_ERR_INVALID, "%s: cell_size %g < cutoff %g", fn, p->cell_size, p->cutoff);
+    a->m = p->m;
+    a->max_iter = p->max_iter;
+    a->max_halvings = p->max_halvings;
+    a->ftol_window = p->ftol_window;
+    a->c1 = p->c1;
+    a->eps_curv = p->eps_curv;
+    a->h_req = (float)((p->cell_size > 0.f ? p->cell_size : p->cutoff) * (1.0 + 1e-4));
+    a->g_tol = p->g_tol;
+    a->ftol = p->ftol;
+    a->rad = (float)rad;
+    a->c2 = (double)p->cutoff * (double)p->cutoff;
+    const double skin = (double)p->skin_half < room ? (double)p->skin_half : room;
+    a->skin2 = skin * skin;
+    a->e_feasible = p->e_feasible;
+    a->tau64 = p->tau64;
+    return PECC_OK;
+}
+
+}  // namespace
+
+int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
+                       pecc_descent_result *out, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream)
+{
+    const char *fn = "pecc_lbfgs_descend";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
     size_t need = 0;
     pecc_lbfgs_descend_workspace_size(inst, &need);
     if (!workspace || workspace_bytes < need)
         return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
-
-    pecc::DescentArgs a;
-    a.m = p->m;
-    a.max_iter = p->max_iter;
-    a.max_halvings = p->max_halvings;
-    a.ftol_window = p->ftol_window;
-    a.c1 = p->c1;
-    a.eps_curv = p->eps_curv;
-    a.h_req = (float)((p->cell_size > 0.f ? p->cell_size : p->cutoff) * (1.0 + 1e-4));
-    a.g_tol = p->g_tol;
-    a.ftol = p->ftol;
-    a.rad = (float)rad;
-    a.c2 = (double)p->cutoff * (double)p->cutoff;
-    const double skin = (double)p->skin_half < room ? (double)p->skin_half : room;
-    a.skin2 = skin * skin;
-    a.e_feasible = p->e_feasible;
-    a.tau64 = p->tau64;
     const int grid = pecc::descend_grid(inst->num_instances);
     return check_hip(pecc::launch_descend(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
                                           inst->total_n, a, out, (int32_t *)workspace, grid,
                                           stream),
+                     fn);
+}
+
+int pecc_gbo_descend_workspace_size(const pecc_instances *inst, int32_t blocks, size_t *bytes)
+{
+    const char *fn = "pecc_gbo_descend_workspace_size";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!bytes) return fail(PECC_ERR_INVALID, "%s: bytes is NULL", fn);
+    if (blocks < 1 || blocks > 8) return fail(PECC_ERR_INVALID, "%s: blocks = %d outside [1, 8]", fn, blocks);
+    *bytes = align256(pecc::gbo_workspace_bytes(inst->num_instances, blocks) + 256);
+    return PECC_OK;
+}
+
+int pecc_gbo_descend(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
+                     int32_t blocks, int32_t sweep_fp64, pecc_descent_result *out,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    const char *fn = "pecc_gbo_descend";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    if (blocks < 1 || blocks > 8) return fail(PECC_ERR_INVALID, "%s: blocks = %d outside [1, 8]", fn, blocks);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
+    size_t need = 0;
+    pecc_gbo_descend_workspace_size(inst, blocks, &need);
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace must be 256-byte aligned", fn);
+    return check_hip(pecc::launch_gbo(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
+                                      inst->total_n, a, blocks, sweep_fp64 ? 1 : 0, out, workspace,
+                                      stream),
                      fn);
 }
 

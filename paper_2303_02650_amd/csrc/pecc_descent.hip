@@ -19,33 +19,14 @@
 // is empty (the launch is sized to the resident capacity of the device).
 #include "pecc_device.hpp"
 #include "pecc_launch.hpp"
+#include "pecc_lbfgs.hpp"
 
 namespace pecc {
 
 constexpr int kDB = 512;                  // threads per workgroup
 constexpr int kDW = kDB / kWave;          // waves per workgroup
 constexpr int kCPT = kMaxN / kDB;         // circles per thread
-constexpr int kMM = 10;                   // history slots (max m)
-constexpr int kNB = 2 * kMM + 1;          // basis size: s_0..s_9, y_0..y_9, g
 constexpr int kEll = 24;                  // neighbor slots per circle (ELL list)
-constexpr int kG = 2 * kMM;               // basis index of g
-
-// Slots of the fused reduction.  gt: trial gradient, sc = xt - x, yc = gt - g.
-constexpr int sGS(int j) { return j; }                      // gt . s_j
-constexpr int sGY(int j) { return kMM + j; }                // gt . y_j
-constexpr int sSS(int j) { return 2 * kMM + j - 1; }        // sc . s_j   (j >= 1)
-constexpr int sSY(int j) { return 3 * kMM - 1 + j - 1; }    // sc . y_j   (j >= 1)
-constexpr int sYS(int j) { return 4 * kMM - 2 + j - 1; }    // yc . s_j   (j >= 1)
-constexpr int sYY(int j) { return 5 * kMM - 3 + j - 1; }    // yc . y_j   (j >= 1)
-constexpr int sGG = 6 * kMM - 4;                            // gt . gt
-constexpr int sScSc = sGG + 1;                              // sc . sc
-constexpr int sScYc = sGG + 2;                              // sc . yc
-constexpr int sYcYc = sGG + 3;                              // yc . yc
-constexpr int sScG = sGG + 4;                               // sc . gt
-constexpr int sYcG = sGG + 5;                               // yc . gt
-constexpr int sE = sGG + 6;                                 // trial energy (radius rad)
-constexpr int sE1 = sGG + 7;                                // trial energy of unit circles
-static_assert(sE1 < kWave, "fused reduction must fit one slot per lane");
 
 struct DescentShared {
     float2 pos[kMaxN];
@@ -64,246 +45,6 @@ struct DescentShared {
     int over;                      // a circle had more than kEll neighbors
     int work;
 };
-
-// Layout-identical mirror of pecc_descent_result.
-struct DescentResultDev {
-    int32_t status, iters, evals, rebuilds;
-    int64_t pair_evals;
-    float E32, gnorm;
-    double E64;
-};
-
-__device__ __forceinline__ float dot2(float2 a, float2 b) { return a.x * b.x + a.y * b.y; }
-
-// Value of reduction slot v summed over this thread's circles (v is a
-// constant after unrolling, so the branches fold away).
-__device__ __forceinline__ float slot_value(int v, const float2 (&gt)[kCPT], const float2 (&sc)[kCPT],
-                                            const float2 (&yc)[kCPT],
-                                            const float2 (&S)[kMM][kCPT],
-                                            const float2 (&Y)[kMM][kCPT], float e, float e1)
-{
-    if (v == sE) return e;
-    if (v == sE1) return e1;
-    float acc = 0.0f;
-#pragma unroll
-    for (int c = 0; c < kCPT; ++c) {
-        float t;
-        if (v < kMM) t = dot2(gt[c], S[v][c]);
-        else if (v < 2 * kMM) t = dot2(gt[c], Y[v - kMM][c]);
-        else if (v < 3 * kMM - 1) t = dot2(sc[c], S[v - 2 * kMM + 1][c]);
-        else if (v < 4 * kMM - 2) t = dot2(sc[c], Y[v - (3 * kMM - 1) + 1][c]);
-        else if (v < 5 * kMM - 3) t = dot2(yc[c], S[v - (4 * kMM - 2) + 1][c]);
-        else if (v < 6 * kMM - 4) t = dot2(yc[c], Y[v - (5 * kMM - 3) + 1][c]);
-        else if (v == sGG) t = dot2(gt[c], gt[c]);
-        else if (v == sScSc) t = dot2(sc[c], sc[c]);
-        else if (v == sScYc) t = dot2(sc[c], yc[c]);
-        else if (v == sYcYc) t = dot2(yc[c], yc[c]);
-        else if (v == sScG) t = dot2(sc[c], gt[c]);
-        else t = dot2(yc[c], gt[c]);   // sYcG
-        acc += t;
-    }
-    return acc;
-}
-
-// ---------------------------------------------------------------------------
-// Cross-lane moves.  DPP (data-parallel primitives) patterns run at VALU
-// rate; quad_perm and the row mirrors stay inside 16-lane rows, row_bcast
-// crosses rows.  Lane builtins work on 32-bit integers, so floats travel as
-// bit patterns.
-// ---------------------------------------------------------------------------
-constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
-constexpr int kDppRowMirror = 0x140;  // lane i <- 15-i inside a row
-constexpr int kDppHalfMirror = 0x141; // lane i <- 7-i inside half a row
-constexpr int kDppBcast15 = 0x142;    // lane 15 of row r -> row r+1
-constexpr int kDppBcast31 = 0x143;    // lane 31 -> rows 2 and 3
-
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ float dpp(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 CTRL, ROW_MASK, 0xf, false));
-}
-
-__device__ __forceinline__ float uniform_first(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float lane_value(float v, int l)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-
-// Sum over the 64 lanes, returned wave-uniform.  Every wave adds in the same
-// order, so every wave gets the same bits.
-__device__ __forceinline__ float wave_sum_dpp(float v)
-{
-    v += dpp<kDppXor1>(v);
-    v += dpp<kDppXor2>(v);
-    v += dpp<kDppHalfMirror>(v);
-    v += dpp<kDppRowMirror>(v);          // every lane of a row holds the row sum
-    v += dpp<kDppBcast15, 0xa>(v);       // rows 1, 3 add rows 0, 2
-    v += dpp<kDppBcast31, 0xc>(v);       // rows 2, 3 add lane 31 (rows 0 + 1)
-    return lane_value(v, 63);
-}
-
-// Slot held by lane L after wave_reduce_scatter (stages decided by lane bits
-// 3, 2, 1, 0, 4, 5 in this order).
-__device__ __forceinline__ int lane_slot(int L)
-{
-    return 32 * ((L >> 3) & 1) + 16 * ((L >> 2) & 1) + 8 * ((L >> 1) & 1) + 4 * (L & 1) +
-           2 * ((L >> 4) & 1) + ((L >> 5) & 1);
-}
-
-// Reduce-scatter of the 64 slot values over the wave: afterwards lane L
-// holds the wave sum of slot lane_slot(L).  Each stage pairs a lane with a
-// partner holding the same slot subset; the lane whose deciding bit is set
-// keeps the upper half.  Partners: stage 1 row mirror (bit 3), stage 2 half
-// mirror (bit 2), stage 3 xor 2, stage 4 xor 1 (all DPP), stage 5 xor 16,
-// stage 6 xor 32 (shuffles).  Slots are produced in the order the first three
-// stages consume them (u, u+8, ..., u+56) so only 8 values are live at once.
-__device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[kCPT],
-                                                     const float2 (&sc)[kCPT],
-                                                     const float2 (&yc)[kCPT],
-                                                     const float2 (&S)[kMM][kCPT],
-                                                     const float2 (&Y)[kMM][kCPT], float e,
-                                                     float e1)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
-    const bool b0 = (lane & 1) != 0, b4 = (lane & 16) != 0, b5 = (lane & 32) != 0;
-    float h[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        float t1[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float lo = slot_value(u + 8 * k, gt, sc, yc, S, Y, e, e1);
-            const float hi = slot_value(u + 8 * k + 32, gt, sc, yc, S, Y, e, e1);
-            t1[k] = (b3 ? hi : lo) + dpp<kDppRowMirror>(b3 ? lo : hi);
-        }
-        float t2[2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-            t2[k] = (b2 ? t1[k + 2] : t1[k]) + dpp<kDppHalfMirror>(b2 ? t1[k] : t1[k + 2]);
-        h[u] = (b1 ? t2[1] : t2[0]) + dpp<kDppXor2>(b1 ? t2[0] : t2[1]);
-        // keep the streaming order: the next group is not hoisted above here
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) h[v] = (b0 ? h[v + 4] : h[v]) + dpp<kDppXor1>(b0 ? h[v] : h[v + 4]);
-#pragma unroll
-    for (int v = 0; v < 2; ++v) h[v] = (b4 ? h[v + 2] : h[v]) + __shfl_xor(b4 ? h[v] : h[v + 2], 16, kWave);
-    return (b5 ? h[1] : h[0]) + __shfl_xor(b5 ? h[0] : h[1], 32, kWave);
-}
-
-// Which vector basis index a of the updated basis is: 0 = an old basis
-// vector (index in *old), 1 = sc, 2 = yc, 3 = gt.
-__device__ __forceinline__ int new_basis_kind(int a, bool push, int *old)
-{
-    if (a == kG) return 3;
-    if (push) {
-        if (a < kMM) {
-            if (a == kMM - 1) return 1;
-            *old = a + 1;
-            return 0;
-        }
-        if (a == 2 * kMM - 1) return 2;
-        *old = a + 1;
-        return 0;
-    }
-    *old = a;
-    return 0;
-}
-
-// Slot holding <kind-vector, old basis vector o>, kind in {1,2,3}.
-__device__ __forceinline__ int slot_new_old(int kind, int o)
-{
-    const bool is_s = o < kMM;
-    const int j = is_s ? o : o - kMM;
-    if (kind == 3) return is_s ? sGS(j) : sGY(j);
-    if (kind == 1) return is_s ? sSS(j) : sSY(j);
-    return is_s ? sYS(j) : sYY(j);
-}
-
-__device__ __forceinline__ int slot_new_new(int ka, int kb)
-{
-    if (ka > kb) { const int t = ka; ka = kb; kb = t; }
-    if (ka == 1 && kb == 1) return sScSc;
-    if (ka == 1 && kb == 2) return sScYc;
-    if (ka == 2 && kb == 2) return sYcYc;
-    if (ka == 1 && kb == 3) return sScG;
-    if (ka == 2 && kb == 3) return sYcG;
-    return sGG;
-}
-
-// Where entry ent = a * kNB + l of the updated Gram matrix comes from:
-// an old entry (index < 0x8000) or a reduction slot (0x8000 + slot).
-__device__ __forceinline__ uint16_t gram_source(int ent, bool push)
-{
-    const int a = ent / kNB, l = ent - a * kNB;
-    int oa = 0, ol = 0;
-    const int ka = new_basis_kind(a, push, &oa);
-    const int kl = new_basis_kind(l, push, &ol);
-    if (ka == 0 && kl == 0) return (uint16_t)(oa * kNB + ol);
-    int sl;
-    if (ka == 0) sl = slot_new_old(kl, oa);
-    else if (kl == 0) sl = slot_new_old(ka, ol);
-    else sl = slot_new_new(ka, kl);
-    return (uint16_t)(0x8000 + sl);
-}
-
-// FP64 neighbor predicate with an FP32 pre-test.  FP32 evaluation of
-// dx*dx + dy*dy carries a relative error below 3e-7, so outside a band of
-// +-1e-5 around c2 its answer is the FP64 one; inside the band the FP64
-// predicate itself decides.  Same pair set as near64, fewer FP64 ops.
-__device__ __forceinline__ bool near_cut(float2 a, float2 b, float c2lo, float c2hi, double c2)
-{
-    const float dx = a.x - b.x, dy = a.y - b.y;
-    const float l2 = dx * dx + dy * dy;
-    if (l2 < c2lo) return true;
-    if (l2 > c2hi) return false;
-    return near64(a, b, c2);
-}
-
-// FP32 pair term of circle i (at q) with circle j (at pj): energy on the
-// i < j side only, gradient of circle i always.  Branch-free (selects only):
-// non-overlapping pairs give d = 0, coincident centres d = 2 rad with no
-// gradient.  (With branches the compiler merges the accumulations into one
-// store through a selected address and moves the accumulators to memory.)
-__device__ __forceinline__ void pair_term32(float2 q, float2 pj, bool count_e, float two_r,
-                                            float four_r2, float &e, float &e1, float &gx,
-                                            float &gy)
-{
-    const float dx = q.x - pj.x, dy = q.y - pj.y;
-    const float l2 = dx * dx + dy * dy;
-    const bool ov = l2 < four_r2;
-    const float il = (ov && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
-    const float d = ov ? two_r - l2 * il : 0.f;
-    // the same pair for unit circles (rad <= the descent's radius): overlap
-    // 2 - l, which is d - (two_r - 2) whenever it is positive
-    const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
-    e += count_e ? d * d : 0.f;
-    e1 += count_e ? d1 * d1 : 0.f;
-    const float kf = -2.f * d * il;
-    gx += kf * dx;
-    gy += kf * dy;
-}
-
-// FP64 pair energies (descent objective, unit circles) of a pair i < j.
-__device__ __forceinline__ void pair_term64(float2 q, float2 pj, double two_r64, double four_r2_64,
-                                            double &eo, double &et)
-{
-    const double ex = (double)q.x - (double)pj.x, ey = (double)q.y - (double)pj.y;
-    const double m2 = ex * ex + ey * ey;
-    if (m2 < four_r2_64) {
-        const double l = sqrt(m2);
-        const double d = two_r64 - l;
-        const double dt = m2 < 4.0 ? 2.0 - l : 0.0;
-        eo += d * d;
-        et += dt * dt;
-    }
-}
 
 // Evaluation requests of the descent's state machine.
 enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2 };
@@ -780,6 +521,12 @@ int descend_grid(int B)
     }
     const int cap = cus * per_cu;
     return B < cap ? B : cap;
+}
+
+hipError_t launch_queue_init(const int32_t *offset, int B, int32_t *queue, hipStream_t s)
+{
+    queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
+    return hipGetLastError();
 }
 
 hipError_t launch_descend(const int32_t *offset, const float *R, const double *R64, float *xy,

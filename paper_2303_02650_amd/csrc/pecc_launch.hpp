@@ -34,4 +34,10 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
 
 int descend_grid(int B);   // persistent workgroups to launch for B instances
 
+// Geometric batch descent: workspace bytes and launch.
+size_t gbo_workspace_bytes(int B, int blocks);
+hipError_t launch_gbo(const int32_t *offset, const float *R, const double *R64, float *xy, int B,
+                      int64_t total_n, const DescentArgs &a, int blocks, int sweep_fp64, void *out,
+                      void *ws, hipStream_t s);
+
 }  // namespace pecc

@@ -1,0 +1,113 @@
+"""GPU parity of the geometric batch descent (Alg. 1, Eq. 7) against the
+oracle's batch descent (same partition, colour order, line search and
+displacement cap, FP64)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2303_02650_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def to_dev(P, inst):
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    return d, torch.from_numpy(inst.xy.reshape(-1)).cuda()
+
+
+def run(P, inst, params, blocks, fp64=False):
+    d, xy = to_dev(P, inst)
+    res = P.results(P.gbo_descend(d, xy, params, blocks=blocks, sweep_fp64=fp64))
+    return xy.cpu().numpy().reshape(-1, 2), res
+
+
+CASES = {
+    "C4x3": (lambda: synth.C4(3), 4),
+    "C1": (lambda: synth.C1(), 2),
+    "C2": (lambda: synth.C2(1), 4),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("outer", [1, 2])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_gbo_first_outer_iterations_follow_oracle(P, name, outer, fp64):
+    mk, blocks = CASES[name]
+    inst = mk()
+    params = P.DescentParams(max_iter=outer, g_tol=0.0, ftol=0.0)
+    xg, res = run(P, inst, params, blocks, fp64)
+    for b in range(inst.B):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                         oracle.DescentParams(g_tol=0.0), blocks=blocks,
+                                         max_outer=outer, skin_half=0.15)
+        assert res["iters"][b] == r64["outer"]
+        scale = max(1.0, float(np.abs(x64).max()))
+        err = np.abs(xg[o0:o1] - x64).max() / scale
+        assert err < 5e-5 * outer, (name, b, err)
+        # the batch gradient norms of the last outer iteration
+        assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-3)
+
+
+def test_gbo_deterministic_and_batch_independent(P):
+    inst = synth.C4(4)
+    params = P.DescentParams(max_iter=60)
+    x1, r1 = run(P, inst, params, 4)
+    x2, r2 = run(P, inst, params, 4)
+    assert np.array_equal(x1, x2) and r1.tobytes() == r2.tobytes()
+    one = synth.pack([inst.instance(2)], [inst.R[2]])
+    x3, r3 = run(P, one, params, 4)
+    assert np.array_equal(x3, x1[inst.offset[2]:inst.offset[3]])
+    assert r3[0].tobytes() == r1[2].tobytes()
+
+
+def test_gbo_energy_non_increasing_and_reported(P):
+    inst = synth.C4(2)
+    E0 = [oracle.energy(inst.instance(b).astype(np.float64), inst.R[b]) for b in range(2)]
+    for outer in (5, 20, 80):
+        xg, res = run(P, inst, P.DescentParams(max_iter=outer, g_tol=0.0, ftol=0.0), 4)
+        for b in range(2):
+            o0, o1 = inst.offset[b], inst.offset[b + 1]
+            E = oracle.energy(xg[o0:o1].astype(np.float64), inst.R[b])
+            assert E <= E0[b] * (1 + 1e-6)
+            assert res["E32"][b] == pytest.approx(E, rel=1e-4)
+            E0[b] = E
+
+
+def test_gbo_whole_descents_reach_oracle_outcomes(P):
+    inst = synth.C4(8)
+    params = P.DescentParams(max_iter=3000, contact_margin=1e-4)
+    xg, res = run(P, inst, params, 4)
+    d, xy = to_dev(P, inst)
+    xy.copy_(torch.from_numpy(xg.reshape(-1)))
+    e64, _, _, f = [t.cpu().numpy() for t in P.verify(d, xy)]
+    assert (f == (res["status"] == 1)).all()
+    ours = np.where(f == 1, 0.0, e64)
+    ref = []
+    for b in range(inst.B):
+        _, r, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                     oracle.DescentParams(ftol=1e-7), blocks=4, max_outer=3000)
+        ref.append(0.0 if r["status"] == "FEASIBLE" else r["E"])
+    # same local-minimum statistics (trajectories part ways): median final
+    # energies within a factor of 3, feasible counts within 3
+    assert abs(int((ours == 0).sum()) - int((np.array(ref) == 0).sum())) <= 3
+    if np.median(ref) > 0:
+        assert np.median(ours) <= 3 * np.median(ref) + 1e-6
+
+
+def test_gbo_block_over_capacity_is_reported(P):
+    # 200 circles in one block of a 2 x 2 grid
+    rng = synth.rng_for(1)
+    xy = 2.0 + rng.random((200, 2)) * 10.0
+    inst = synth.pack([xy, synth.disk_uniform(50, 6.0, rng)], [30.0, 6.0])
+    _, res = run(P, inst, P.DescentParams(max_iter=5), 2)
+    assert res["status"][0] == 7
+    assert res["status"][1] in (1, 2, 3, 4, 5)
