@@ -15,6 +15,16 @@ arrays through ctypes.  Each function names the part of the paper it follows:
   descend            Alg. 1 with one batch, L-BFGS reading of Eq. 8-11
   gbo_descend        Alg. 1 with geometric batches (2D grid blocks, 4 colours)
   verify             Eq. 1-2 checked through E (Eq. 5) in FP64
+
+The learned proposal of the perturbation step (Sec. 5, Alg. 5) lives in
+``pecc_oracle_lp.c``; the network is the project's own definition:
+
+  bf16_round         FP32 -> BF16 round-to-nearest-even
+  features           8 local features of a candidate (circle, destination)
+  mlp_forward        8 -> 64 -> 64 -> 1 erf-GELU network, FP64
+  mlp_grad           mean BCE-with-logits loss and its gradient, FP64
+  adam               one Adam step, FP64
+  propose            top-k distinct circles by score, and their relocation
 """
 from __future__ import annotations
 
@@ -26,7 +36,7 @@ from dataclasses import dataclass, asdict
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "pecc_oracle.c")
+_SRCS = [os.path.join(_HERE, "pecc_oracle.c"), os.path.join(_HERE, "pecc_oracle_lp.c")]
 _LIB = os.path.join(_HERE, "_pecc_oracle.so")
 
 STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED",
@@ -35,13 +45,18 @@ STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED",
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, FP64, no contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
                                "-std=c99", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def _stale() -> bool:
+    return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                           for f in _SRCS)
 
 
 _lib = None
@@ -50,7 +65,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = C.CDLL(_LIB)
         dp, fp, ip = C.POINTER(C.c_double), C.POINTER(C.c_float), C.POINTER(C.c_int32)
@@ -71,6 +86,20 @@ def lib():
         L.oracle_gbo_descend.restype = C.c_int
         L.oracle_gbo_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_void_p,
                                          C.c_void_p, dp]
+        i64 = C.c_int64
+        L.oracle_bf16_round.restype = None
+        L.oracle_bf16_round.argtypes = [i64, fp, fp]
+        L.oracle_features.restype = C.c_int
+        L.oracle_features.argtypes = [C.c_int, fp, C.c_double, C.c_int, ip, fp, dp]
+        L.oracle_mlp_forward.restype = None
+        L.oracle_mlp_forward.argtypes = [dp, C.c_int, i64, dp, dp]
+        L.oracle_mlp_grad.restype = C.c_double
+        L.oracle_mlp_grad.argtypes = [dp, C.c_int, i64, dp, dp, dp]
+        L.oracle_adam.restype = None
+        L.oracle_adam.argtypes = [C.c_int, dp, dp, dp, dp, C.c_int, C.c_double, C.c_double,
+                                  C.c_double, C.c_double]
+        L.oracle_propose.restype = C.c_int
+        L.oracle_propose.argtypes = [C.c_int, fp, C.c_int, ip, fp, fp, C.c_int, ip, fp]
         _lib = L
     return _lib
 
@@ -236,3 +265,89 @@ def gbo_descend(xy, R: float, params: DescentParams | None = None, blocks: int =
     if trace:
         tr = tr[:cr.outer + 1]
     return x, res, tr
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal (pecc_oracle_lp.c)
+# ---------------------------------------------------------------------------
+N_FEATURES, N_HIDDEN, N_PARAMS = 8, 64, 4801
+# offsets of W1 [64][8], b1, W2 [64][64], b2, W3 [64], b3 in the flat vector
+PARAM_SLICES = {"W1": (0, 512), "b1": (512, 576), "W2": (576, 4672), "b2": (4672, 4736),
+                "W3": (4736, 4800), "b3": (4800, 4801)}
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def bf16_round(w):
+    """FP32 -> BF16 (round to nearest even), returned as float32."""
+    w, pw = _f(np.asarray(w, dtype=np.float32).reshape(-1))
+    out = np.empty_like(w)
+    lib().oracle_bf16_round(w.size, pw, out.ctypes.data_as(C.POINTER(C.c_float)))
+    return out
+
+
+def features(xy32, R: float, cand_circle, cand_dest):
+    """(ncand, 8) FP64 features of candidates (circle index, destination)."""
+    xy, px = _f(np.asarray(xy32, dtype=np.float32).reshape(-1, 2))
+    cc, pc = _i(np.asarray(cand_circle).reshape(-1))
+    cd, pd = _f(np.asarray(cand_dest, dtype=np.float32).reshape(-1, 2))
+    out = np.zeros((cc.size, 8), dtype=np.float64)
+    rc = lib().oracle_features(xy.shape[0], px, float(R), cc.size, pc, pd,
+                               out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ValueError("candidate circle index out of range")
+    return out
+
+
+def mlp_forward(params, x, round_bf16: bool = True):
+    """Logits (rows,) of the network at parameters ``params`` (4801,)."""
+    p, pp = _d(np.asarray(params).reshape(-1))
+    assert p.size == N_PARAMS
+    x, px = _d(np.asarray(x).reshape(-1, N_FEATURES))
+    z = np.zeros(x.shape[0], dtype=np.float64)
+    lib().oracle_mlp_forward(pp, 1 if round_bf16 else 0, x.shape[0], px,
+                             z.ctypes.data_as(C.POINTER(C.c_double)))
+    return z
+
+
+def mlp_grad(params, x, y, round_bf16: bool = True):
+    """(loss, grad (4801,)) of the mean BCE-with-logits loss."""
+    p, pp = _d(np.asarray(params).reshape(-1))
+    assert p.size == N_PARAMS
+    x, px = _d(np.asarray(x).reshape(-1, N_FEATURES))
+    y, py = _d(np.asarray(y).reshape(-1))
+    g = np.zeros(N_PARAMS, dtype=np.float64)
+    loss = lib().oracle_mlp_grad(pp, 1 if round_bf16 else 0, x.shape[0], px, py,
+                                 g.ctypes.data_as(C.POINTER(C.c_double)))
+    return loss, g
+
+
+def adam(params, m, v, grad, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
+         eps: float = 1e-8):
+    """One Adam step on copies; returns (params, m, v)."""
+    p, pp = _d(np.array(params, dtype=np.float64, copy=True).reshape(-1))
+    m, pm = _d(np.array(m, dtype=np.float64, copy=True).reshape(-1))
+    v, pv = _d(np.array(v, dtype=np.float64, copy=True).reshape(-1))
+    g, pg = _d(np.asarray(grad).reshape(-1))
+    lib().oracle_adam(p.size, pp, pm, pv, pg, int(t), float(lr), float(b1), float(b2), float(eps))
+    return p, m, v
+
+
+def propose(xy32, cand_circle, cand_dest, scores, k: int):
+    """Top-k distinct circles; returns (selected candidate indices, relocated xy)."""
+    xy, px = _f(np.asarray(xy32, dtype=np.float32).reshape(-1, 2))
+    cc, pc = _i(np.asarray(cand_circle).reshape(-1))
+    cd, pd = _f(np.asarray(cand_dest, dtype=np.float32).reshape(-1, 2))
+    if scores is not None:
+        sc, ps = _f(np.asarray(scores, dtype=np.float32).reshape(-1))
+    else:
+        ps = None
+    sel = np.zeros(max(int(k), 1), dtype=np.int32)
+    out = np.zeros_like(xy)
+    cnt = lib().oracle_propose(xy.shape[0], px, cc.size, pc, pd, ps, int(k),
+                               sel.ctypes.data_as(C.POINTER(C.c_int32)),
+                               out.ctypes.data_as(C.POINTER(C.c_float)))
+    return sel[:cnt], out
