@@ -210,6 +210,112 @@ int pecc_verify(const pecc_instances *inst, const float *xy, double tol,
                 double *energy64, double *max_pair_overlap, double *max_cont_overlap,
                 int32_t *feasible, hipStream_t stream);
 
+/* ========================================================================
+ * Learned proposal for the perturbation step of SED (Sec. 5, Alg. 5).
+ *
+ * SED perturbs the current layout and descends again.  Here the
+ * perturbation relocates k distinct circles; a candidate is a pair
+ * (circle i, destination q), q drawn by the caller uniformly in the disk of
+ * radius R - 1.  A small network scores candidates from local features and
+ * the k best-scored distinct circles move to their candidates' points.  The
+ * network is the project's addition (the paper perturbs every circle by a
+ * random shift); uniform random choice is the fallback, and the descent's
+ * final FP64 energy is the judge (pecc_accept).
+ * ======================================================================== */
+#define PECC_FEATURES     8     /* features per candidate                       */
+#define PECC_MLP_PARAMS   4801  /* network parameters (layout below)            */
+
+/* Features of candidates: for instance b, candidate c (0 <= c < C) names the
+ * local circle cand_circle[b*C + c] (0-based within the instance) and the
+ * point cand_dest[2*(b*C + c) + {0,1}].  Output features[8*(b*C + c) + f]:
+ *   f = 0..3 around the circle's own centre, 4..7 around the destination,
+ *   each time over the other circles j != i (i lifted out):
+ *   0/4  overlap energy e of a unit circle there (sum over j of
+ *        max(0, 2 - l)^2 plus max(0, rho + 1 - R)^2), as log10(e + 1e-20)/20 + 1
+ *   1/5  number of j with l < 2.3
+ *   2/6  boundary gap (R - 1 - rho) / R
+ *   3/7  number of j with l < 4, divided by 16 pi
+ * Distances are FP64 on the FP32 coordinates (counts are exact); results
+ * are rounded to FP32.  A candidate whose circle index is outside
+ * [0, n_b) gets NaN features.  Errors: PECC_ERR_INVALID for null pointers,
+ * C < 0 or B*C >= 2^31. */
+int pecc_features(const pecc_instances *inst, const float *xy, int32_t cands_per_inst,
+                  const int32_t *cand_circle, const float *cand_dest, float *features,
+                  hipStream_t stream);
+
+/* Network 8 -> 64 -> 64 -> 1 with GELU(t) = t Phi(t) (erf form) after both
+ * hidden layers.  params: FP32 master values, device [PECC_MLP_PARAMS]:
+ *   W1 [64][8] at 0, b1 [64] at 512, W2 [64][64] at 576, b2 [64] at 4672,
+ *   W3 [64] at 4736, b3 at 4800  (W[out][in], row-major).
+ * The weight matrices are used as their BF16 roundings (nearest even);
+ * biases stay FP32.  Products run on BF16 matrix cores with FP32
+ * accumulation, hidden activations enter them as BF16.
+ * features: device [rows][8] FP32; logits: device [rows] FP32 (the score).
+ * Errors: PECC_ERR_INVALID for rows < 0 or null pointers (rows > 0). */
+int pecc_mlp_forward(const float *params, const float *features, int64_t rows, float *logits,
+                     hipStream_t stream);
+
+/* Workspace of pecc_mlp_grad / pecc_mlp_train_step for a given row count. */
+int pecc_mlp_grad_workspace_size(int64_t rows, size_t *bytes);
+
+/* Mean binary cross-entropy of sigmoid(logit) against labels (device
+ * [rows], values 0 or 1) and its gradient with respect to the parameters as
+ * used (the BF16 weights; apply it to the FP32 masters).  loss: device [1]
+ * (nullable); grad: device [PECC_MLP_PARAMS].  Per-workgroup partial sums
+ * are added in a fixed order: the result does not depend on timing.
+ * rows = 0 gives loss 0 and a zero gradient.  Errors: PECC_ERR_INVALID,
+ * PECC_ERR_WORKSPACE. */
+int pecc_mlp_grad(const float *params, const float *features, const float *labels, int64_t rows,
+                  float *loss, float *grad, void *ws, size_t ws_bytes, hipStream_t stream);
+
+typedef struct pecc_adam_params {
+    float lr;       /* step size (1e-3)                                           */
+    float beta1;    /* first-moment decay (0.9)                                   */
+    float beta2;    /* second-moment decay (0.999)                                */
+    float eps;      /* denominator guard (1e-8)                                   */
+} pecc_adam_params;
+
+/* One Adam step (Kingma & Ba, bias-corrected) on FP32 params, moments m and
+ * v (device [PECC_MLP_PARAMS] each, zero before the first step).  step:
+ * device int32 [1], the number of steps taken so far; the call uses
+ * t = *step + 1 and then stores t, so it can be replayed from a graph.
+ * Errors: PECC_ERR_INVALID for null pointers, lr < 0, beta outside [0, 1),
+ * eps <= 0. */
+int pecc_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t *step,
+                  const pecc_adam_params *hp, hipStream_t stream);
+
+/* pecc_mlp_grad followed by pecc_mlp_adam on the same stream; grad is the
+ * caller's buffer for the gradient in between. */
+int pecc_mlp_train_step(float *params, float *m, float *v, int32_t *step,
+                        const pecc_adam_params *hp, const float *features, const float *labels,
+                        int64_t rows, float *loss, float *grad, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Proposal.  Per instance: every circle named by a candidate is represented
+ * by its best candidate (highest score, the lower candidate index among
+ * equal scores); circles are ranked by that score, equal scores by the lower
+ * candidate index, and the first k (or as many distinct circles as there
+ * are) are chosen.  scores: device [B*C] or NULL; NULL, or a NaN among an
+ * instance's scores, makes all of that instance's scores equal: the choice is
+ * then the first k distinct circles in candidate order, a uniform random
+ * subset for uniformly drawn candidates.  Candidates naming a circle outside
+ * [0, n_b) are ignored.
+ * xy_out (device, layout of xy; may equal xy) receives xy with each chosen
+ * circle moved to its candidate's destination.  selected (device [B*k],
+ * nullable) receives the chosen candidate indices in rank order, -1 past
+ * the last.  Errors: PECC_ERR_INVALID for null pointers, C < 0, k < 0. */
+int pecc_propose(const pecc_instances *inst, const float *xy, int32_t cands_per_inst,
+                 const int32_t *cand_circle, const float *cand_dest, const float *scores,
+                 int32_t k, int32_t *selected, float *xy_out, hipStream_t stream);
+
+/* Acceptance (SED keeps a candidate layout that lowers the energy): for each
+ * instance with e_new[b] < e_cur[b] (FP64, e.g. pecc_verify's energy64),
+ * copy its circles from xy_new into xy_cur and set e_cur[b] = e_new[b].
+ * accepted: device [B] (nullable), 1 where taken.  A NaN e_new is never
+ * taken. */
+int pecc_accept(const pecc_instances *inst, float *xy_cur, double *e_cur, const float *xy_new,
+                const double *e_new, int32_t *accepted, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

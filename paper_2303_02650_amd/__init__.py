@@ -52,7 +52,15 @@ RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("evals", np
                          ("gnorm", np.float32), ("E64", np.float64)])
 assert RESULT_DTYPE.itemsize == 40
 
+class pecc_adam_params(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+PECC_FEATURES = 8
+PECC_MLP_PARAMS = 4801
+
 _P = C.POINTER
+_V = C.c_void_p
 _sig = {
     "pecc_last_error": (C.c_char_p, []),
     "pecc_version": (C.c_char_p, []),
@@ -72,6 +80,16 @@ _sig = {
     "pecc_gbo_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
+    "pecc_features": (C.c_int, [_P(pecc_instances), _V, C.c_int32, _V, _V, _V, _V]),
+    "pecc_mlp_forward": (C.c_int, [_V, _V, C.c_int64, _V, _V]),
+    "pecc_mlp_grad_workspace_size": (C.c_int, [C.c_int64, _P(C.c_size_t)]),
+    "pecc_mlp_grad": (C.c_int, [_V, _V, _V, C.c_int64, _V, _V, _V, C.c_size_t, _V]),
+    "pecc_mlp_adam": (C.c_int, [_V, _V, _V, _V, _V, _P(pecc_adam_params), _V]),
+    "pecc_mlp_train_step": (C.c_int, [_V, _V, _V, _V, _P(pecc_adam_params), _V, _V, C.c_int64,
+                                      _V, _V, _V, C.c_size_t, _V]),
+    "pecc_propose": (C.c_int, [_P(pecc_instances), _V, C.c_int32, _V, _V, _V, C.c_int32, _V, _V,
+                               _V]),
+    "pecc_accept": (C.c_int, [_P(pecc_instances), _V, _V, _V, _V, _V, _V]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -283,3 +301,138 @@ def verify(inst: DeviceInstances, xy: torch.Tensor, tol: float = 1e-20):
     f = torch.empty(inst.B, dtype=torch.int32, device=dev)
     pecc_verify(inst, xy, tol, e, mp, mc, f)
     return e, mp, mc, f
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal (same names as the C ABI, then conveniences)
+# ---------------------------------------------------------------------------
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def pecc_features(inst, xy, cands_per_inst, cand_circle, cand_dest, features, stream=None):
+    _check(_lib.pecc_features(C.byref(inst.c()), _ptr(xy), int(cands_per_inst), _ptr(cand_circle),
+                              _ptr(cand_dest), _ptr(features), _stream(stream)))
+
+
+def pecc_mlp_forward(params, features, rows, logits, stream=None):
+    _check(_lib.pecc_mlp_forward(_ptr(params), _ptr(features), int(rows), _ptr(logits),
+                                 _stream(stream)))
+
+
+def pecc_mlp_grad_workspace_size(rows: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_mlp_grad_workspace_size(int(rows), C.byref(b)))
+    return b.value
+
+
+def pecc_mlp_grad(params, features, labels, rows, loss, grad, workspace, stream=None):
+    _check(_lib.pecc_mlp_grad(_ptr(params), _ptr(features), _ptr(labels), int(rows), _ptr(loss),
+                              _ptr(grad), _ptr(workspace), _nbytes(workspace), _stream(stream)))
+
+
+def pecc_mlp_adam(params, m, v, grad, step, hp: pecc_adam_params, stream=None):
+    _check(_lib.pecc_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), _ptr(step), C.byref(hp),
+                              _stream(stream)))
+
+
+def pecc_mlp_train_step(params, m, v, step, hp: pecc_adam_params, features, labels, rows, loss,
+                        grad, workspace, stream=None):
+    _check(_lib.pecc_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), _ptr(step), C.byref(hp),
+                                    _ptr(features), _ptr(labels), int(rows), _ptr(loss), _ptr(grad),
+                                    _ptr(workspace), _nbytes(workspace), _stream(stream)))
+
+
+def pecc_propose(inst, xy, cands_per_inst, cand_circle, cand_dest, scores, k, selected, xy_out,
+                 stream=None):
+    _check(_lib.pecc_propose(C.byref(inst.c()), _ptr(xy), int(cands_per_inst), _ptr(cand_circle),
+                             _ptr(cand_dest), _ptr(scores), int(k), _ptr(selected), _ptr(xy_out),
+                             _stream(stream)))
+
+
+def pecc_accept(inst, xy_cur, e_cur, xy_new, e_new, accepted, stream=None):
+    _check(_lib.pecc_accept(C.byref(inst.c()), _ptr(xy_cur), _ptr(e_cur), _ptr(xy_new),
+                            _ptr(e_new), _ptr(accepted), _stream(stream)))
+
+
+def features(inst: DeviceInstances, xy: torch.Tensor, cand_circle: torch.Tensor,
+             cand_dest: torch.Tensor) -> torch.Tensor:
+    """FP32 features [B*C, 8] of C candidates per instance."""
+    C_ = cand_circle.numel() // inst.B
+    out = torch.empty(inst.B * C_, PECC_FEATURES, dtype=torch.float32, device=xy.device)
+    pecc_features(inst, xy, C_, cand_circle, cand_dest, out)
+    return out
+
+
+def mlp_forward(params: torch.Tensor, feats: torch.Tensor) -> torch.Tensor:
+    rows = feats.shape[0]
+    z = torch.empty(rows, dtype=torch.float32, device=feats.device)
+    pecc_mlp_forward(params, feats, rows, z)
+    return z
+
+
+def mlp_grad(params: torch.Tensor, feats: torch.Tensor, labels: torch.Tensor,
+             workspace: torch.Tensor | None = None):
+    """(loss [1], grad [4801]) of the mean BCE-with-logits loss."""
+    rows = feats.shape[0]
+    dev = params.device
+    if workspace is None:
+        workspace = torch.empty(pecc_mlp_grad_workspace_size(rows), dtype=torch.uint8, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    grad = torch.empty(PECC_MLP_PARAMS, dtype=torch.float32, device=dev)
+    pecc_mlp_grad(params, feats, labels, rows, loss, grad, workspace)
+    return loss, grad
+
+
+class MlpTrainer:
+    """FP32 master parameters, Adam moments and the device step counter."""
+
+    def __init__(self, params: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, max_rows: int = 8192):
+        dev = params.device
+        self.params = params.detach().to(torch.float32).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.hp = pecc_adam_params(lr, beta1, beta2, eps)
+        self.ws = torch.empty(pecc_mlp_grad_workspace_size(max_rows), dtype=torch.uint8,
+                              device=dev)
+        self.max_rows = max_rows
+
+    def train_step(self, feats: torch.Tensor, labels: torch.Tensor):
+        rows = feats.shape[0]
+        assert rows <= self.max_rows
+        pecc_mlp_train_step(self.params, self.m, self.v, self.step, self.hp, feats, labels, rows,
+                            self.loss, self.grad, self.ws)
+        return self.loss
+
+
+def init_params(seed: int = 0, device="cuda") -> torch.Tensor:
+    """He-style random initial parameters (zero biases)."""
+    g = np.random.default_rng(seed)
+    p = np.zeros(PECC_MLP_PARAMS, dtype=np.float32)
+    p[0:512] = g.normal(0, np.sqrt(2 / 8), 512)
+    p[576:4672] = g.normal(0, np.sqrt(2 / 64), 4096)
+    p[4736:4800] = g.normal(0, np.sqrt(1 / 64), 64)
+    return torch.from_numpy(p).to(device)
+
+
+def propose(inst: DeviceInstances, xy: torch.Tensor, cand_circle: torch.Tensor,
+            cand_dest: torch.Tensor, scores: torch.Tensor | None, k: int,
+            xy_out: torch.Tensor | None = None):
+    """(relocated layout, selected candidate indices [B, k])."""
+    C_ = cand_circle.numel() // inst.B
+    if xy_out is None:
+        xy_out = torch.empty_like(xy)
+    sel = torch.empty(inst.B, max(k, 1), dtype=torch.int32, device=xy.device)
+    pecc_propose(inst, xy, C_, cand_circle, cand_dest, scores, k, sel, xy_out)
+    return xy_out, sel[:, :k]
+
+
+def accept(inst: DeviceInstances, xy_cur: torch.Tensor, e_cur: torch.Tensor,
+           xy_new: torch.Tensor, e_new: torch.Tensor) -> torch.Tensor:
+    acc = torch.empty(inst.B, dtype=torch.int32, device=xy_cur.device)
+    pecc_accept(inst, xy_cur, e_cur, xy_new, e_new, acc)
+    return acc

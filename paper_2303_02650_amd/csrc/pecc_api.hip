@@ -252,7 +252,148 @@ int pecc_verify(const pecc_instances *inst, const float *xy, double tol, double 
                      fn);
 }
 
+// ---------------------------------------------------------------------------
+// Learned proposal
+// ---------------------------------------------------------------------------
+int pecc_features(const pecc_instances *inst, const float *xy, int32_t cands_per_inst,
+                  const int32_t *cand_circle, const float *cand_dest, float *features,
+                  hipStream_t stream)
+{
+    const char *fn = "pecc_features";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (cands_per_inst < 0) return fail(PECC_ERR_INVALID, "%s: cands_per_inst < 0", fn);
+    if (cands_per_inst == 0) return PECC_OK;
+    if ((int64_t)cands_per_inst * inst->num_instances > 0x7fffffffLL)
+        return fail(PECC_ERR_INVALID, "%s: more than 2^31-1 candidates", fn);
+    if (!xy || !cand_circle || !cand_dest || !features)
+        return fail(PECC_ERR_INVALID, "%s: xy, cand_circle, cand_dest and features must be set",
+                    fn);
+    return check_hip(pecc::launch_features(inst->offset, inst->R, inst->R64, xy,
+                                           inst->num_instances, cands_per_inst, cand_circle,
+                                           cand_dest, features, stream),
+                     fn);
+}
+
+int pecc_mlp_forward(const float *params, const float *features, int64_t rows, float *logits,
+                     hipStream_t stream)
+{
+    const char *fn = "pecc_mlp_forward";
+    if (rows < 0) return fail(PECC_ERR_INVALID, "%s: rows < 0", fn);
+    if (rows == 0) return PECC_OK;
+    if (!params || !features || !logits)
+        return fail(PECC_ERR_INVALID, "%s: params, features and logits must be set", fn);
+    return check_hip(pecc::launch_mlp_forward(params, features, rows, logits, stream), fn);
+}
+
+int pecc_mlp_grad_workspace_size(int64_t rows, size_t *bytes)
+{
+    if (rows < 0 || !bytes) return fail(PECC_ERR_INVALID, "pecc_mlp_grad_workspace_size: bad arguments");
+    *bytes = align256(pecc::mlp_grad_workspace_bytes(rows));
+    return PECC_OK;
+}
+
+static int mlp_grad_checks(const char *fn, const float *params, const float *features,
+                           const float *labels, int64_t rows, const float *grad, const void *ws,
+                           size_t ws_bytes)
+{
+    if (rows < 0) return fail(PECC_ERR_INVALID, "%s: rows < 0", fn);
+    if (!params || !grad) return fail(PECC_ERR_INVALID, "%s: params and grad must be set", fn);
+    if (rows > 0 && (!features || !labels))
+        return fail(PECC_ERR_INVALID, "%s: features and labels must be set", fn);
+    const size_t need = align256(pecc::mlp_grad_workspace_bytes(rows));
+    if (!ws || ws_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    return PECC_OK;
+}
+
+int pecc_mlp_grad(const float *params, const float *features, const float *labels, int64_t rows,
+                  float *loss, float *grad, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const char *fn = "pecc_mlp_grad";
+    int rc = mlp_grad_checks(fn, params, features, labels, rows, grad, ws, ws_bytes);
+    if (rc) return rc;
+    return check_hip(pecc::launch_mlp_grad(params, features, labels, rows, loss, grad, ws, stream),
+                     fn);
+}
+
+static int adam_checks(const char *fn, const float *params, const float *m, const float *v,
+                       const float *grad, const int32_t *step, const pecc_adam_params *hp,
+                       pecc::AdamArgs *a)
+{
+    if (!params || !m || !v || !grad || !step || !hp)
+        return fail(PECC_ERR_INVALID, "%s: params, m, v, grad, step and hp must be set", fn);
+    if (!(hp->lr >= 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) ||
+        !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->eps > 0.0f))
+        return fail(PECC_ERR_INVALID, "%s: need lr >= 0, 0 <= beta < 1, eps > 0", fn);
+    *a = pecc::AdamArgs{hp->lr, hp->beta1, hp->beta2, hp->eps};
+    return PECC_OK;
+}
+
+int pecc_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t *step,
+                  const pecc_adam_params *hp, hipStream_t stream)
+{
+    const char *fn = "pecc_mlp_adam";
+    pecc::AdamArgs a;
+    int rc = adam_checks(fn, params, m, v, grad, step, hp, &a);
+    if (rc) return rc;
+    return check_hip(pecc::launch_adam(params, m, v, grad, step, a, stream), fn);
+}
+
+int pecc_mlp_train_step(float *params, float *m, float *v, int32_t *step,
+                        const pecc_adam_params *hp, const float *features, const float *labels,
+                        int64_t rows, float *loss, float *grad, void *ws, size_t ws_bytes,
+                        hipStream_t stream)
+{
+    const char *fn = "pecc_mlp_train_step";
+    int rc = mlp_grad_checks(fn, params, features, labels, rows, grad, ws, ws_bytes);
+    if (rc) return rc;
+    pecc::AdamArgs a;
+    rc = adam_checks(fn, params, m, v, grad, step, hp, &a);
+    if (rc) return rc;
+    rc = check_hip(pecc::launch_mlp_grad(params, features, labels, rows, loss, grad, ws, stream),
+                   fn);
+    if (rc) return rc;
+    return check_hip(pecc::launch_adam(params, m, v, grad, step, a, stream), fn);
+}
+
+int pecc_propose(const pecc_instances *inst, const float *xy, int32_t cands_per_inst,
+                 const int32_t *cand_circle, const float *cand_dest, const float *scores,
+                 int32_t k, int32_t *selected, float *xy_out, hipStream_t stream)
+{
+    const char *fn = "pecc_propose";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (cands_per_inst < 0 || k < 0)
+        return fail(PECC_ERR_INVALID, "%s: cands_per_inst and k must be >= 0", fn);
+    if ((int64_t)cands_per_inst * inst->num_instances > 0x7fffffffLL)
+        return fail(PECC_ERR_INVALID, "%s: more than 2^31-1 candidates", fn);
+    if (inst->total_n > 0 && (!xy || !xy_out))
+        return fail(PECC_ERR_INVALID, "%s: xy and xy_out must be set", fn);
+    if (cands_per_inst > 0 && (!cand_circle || !cand_dest))
+        return fail(PECC_ERR_INVALID, "%s: cand_circle and cand_dest must be set", fn);
+    return check_hip(pecc::launch_propose(inst->offset, xy, inst->num_instances, cands_per_inst,
+                                          cand_circle, cand_dest, scores, k, selected, xy_out,
+                                          stream),
+                     fn);
+}
+
+int pecc_accept(const pecc_instances *inst, float *xy_cur, double *e_cur, const float *xy_new,
+                const double *e_new, int32_t *accepted, hipStream_t stream)
+{
+    const char *fn = "pecc_accept";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!e_cur || !e_new) return fail(PECC_ERR_INVALID, "%s: e_cur and e_new must be set", fn);
+    if (inst->total_n > 0 && (!xy_cur || !xy_new))
+        return fail(PECC_ERR_INVALID, "%s: xy_cur and xy_new must be set", fn);
+    return check_hip(pecc::launch_accept(inst->offset, xy_cur, e_cur, xy_new, e_new,
+                                         inst->num_instances, accepted, stream),
+                     fn);
+}
+
 }  // extern "C"
 
 static_assert(sizeof(pecc_descent_result) == 40, "result layout");
 static_assert(sizeof(pecc_descent_params) == 64, "params layout");
+static_assert(sizeof(pecc_adam_params) == 16, "adam params layout");

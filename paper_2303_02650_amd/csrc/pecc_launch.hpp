@@ -40,4 +40,24 @@ hipError_t launch_gbo(const int32_t *offset, const float *R, const double *R64, 
                       int64_t total_n, const DescentArgs &a, int blocks, int sweep_fp64, void *out,
                       void *ws, hipStream_t s);
 
+// Learned proposal: features, network forward / gradient, Adam, proposal, acceptance.
+hipError_t launch_features(const int32_t *offset, const float *R, const double *R64,
+                           const float *xy, int B, int C, const int32_t *cand_circle,
+                           const float *cand_dest, float *feat, hipStream_t s);
+hipError_t launch_mlp_forward(const float *params, const float *X, int64_t rows, float *Z,
+                              hipStream_t s);
+size_t mlp_grad_workspace_bytes(int64_t rows);
+hipError_t launch_mlp_grad(const float *params, const float *X, const float *Y, int64_t rows,
+                           float *loss, float *grad, void *ws, hipStream_t s);
+struct AdamArgs {
+    float lr, b1, b2, eps;
+};
+hipError_t launch_adam(float *params, float *m, float *v, const float *grad, int32_t *step,
+                       const AdamArgs &a, hipStream_t s);
+hipError_t launch_propose(const int32_t *offset, const float *xy, int B, int C,
+                          const int32_t *cand_circle, const float *cand_dest, const float *scores,
+                          int k, int32_t *selected, float *xy_out, hipStream_t s);
+hipError_t launch_accept(const int32_t *offset, float *xy_cur, double *e_cur, const float *xy_new,
+                         const double *e_new, int B, int32_t *accepted, hipStream_t s);
+
 }  // namespace pecc

@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "disk_uniform", "square_uniform", "Instances", "pack", "instance_set",
-    "relocation_draws", "apply_relocation", "rng_for",
+    "relocation_draws", "apply_relocation", "rng_for", "candidates",
     "C1", "C2", "C3", "C4", "C5",
 ]
 
@@ -111,6 +111,22 @@ def relocation_draws(n: int, R: float, frac: float, rng: np.random.Generator):
     idx = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
     dest = disk_uniform(k, R, rng)
     return idx, dest
+
+
+def candidates(inst: "Instances", count: int, rng: np.random.Generator):
+    """Candidate relocations of the learned proposal: per instance, count
+    pairs (circle index uniform in [0, n_b), destination uniform in the disk
+    of radius R_b - 1).  Returns cand_circle int32 [B, count] (local indices)
+    and cand_dest float32 [B, count, 2]."""
+    B = inst.B
+    cc = np.zeros((B, count), dtype=np.int32)
+    cd = np.zeros((B, count, 2), dtype=np.float32)
+    for b in range(B):
+        nb = int(inst.offset[b + 1] - inst.offset[b])
+        if nb > 0:
+            cc[b] = rng.integers(0, nb, size=count)
+        cd[b] = disk_uniform(count, float(inst.R[b]), rng)
+    return cc, cd
 
 
 def apply_relocation(xy: np.ndarray, idx: np.ndarray, dest: np.ndarray) -> np.ndarray:

@@ -119,3 +119,30 @@ def test_default_params_match_header(P):
     assert d.m == 10 and d.max_iter == 5000 and d.max_halvings == 40
     assert abs(d.cutoff - 2.3) < 1e-6 and abs(d.skin_half - 0.15) < 1e-7
     assert d.e_feasible == 1e-20 and d.tau64 == 1e-4
+
+
+def test_learned_proposal_entry_points_reject_bad_arguments(P):
+    inst = _fake_inst(P)
+    ptr = C.c_void_p(0x5000)
+    L = P._lib
+    assert L.pecc_features(C.byref(inst), ptr, -1, ptr, ptr, ptr, None) == -1
+    assert L.pecc_features(C.byref(inst), None, 4, ptr, ptr, ptr, None) == -1
+    assert L.pecc_mlp_forward(ptr, ptr, -1, ptr, None) == -1
+    assert L.pecc_mlp_forward(None, ptr, 10, ptr, None) == -1
+    b = C.c_size_t()
+    assert L.pecc_mlp_grad_workspace_size(-1, C.byref(b)) == -1
+    assert L.pecc_mlp_grad_workspace_size(8192, C.byref(b)) == 0 and b.value > 0
+    assert L.pecc_mlp_grad(ptr, ptr, ptr, 8192, ptr, ptr, ptr, b.value - 1, None) == -2
+    assert L.pecc_mlp_grad(ptr, ptr, None, 8192, ptr, ptr, ptr, b.value, None) == -1
+    bad = [P.pecc_adam_params(-1.0, 0.9, 0.999, 1e-8), P.pecc_adam_params(1e-3, 1.0, 0.999, 1e-8),
+           P.pecc_adam_params(1e-3, 0.9, 0.999, 0.0)]
+    for hp in bad:
+        assert L.pecc_mlp_adam(ptr, ptr, ptr, ptr, ptr, C.byref(hp), None) == -1
+    good = P.pecc_adam_params(1e-3, 0.9, 0.999, 1e-8)
+    assert L.pecc_mlp_adam(ptr, ptr, ptr, ptr, None, C.byref(good), None) == -1
+    assert L.pecc_mlp_train_step(ptr, ptr, ptr, ptr, C.byref(bad[0]), ptr, ptr, 10, ptr, ptr, ptr,
+                                 b.value, None) == -1
+    assert L.pecc_propose(C.byref(inst), ptr, 4, ptr, ptr, None, -1, ptr, ptr, None) == -1
+    assert L.pecc_propose(C.byref(inst), ptr, 4, ptr, ptr, None, 3, ptr, None, None) == -1
+    assert L.pecc_accept(C.byref(inst), ptr, None, ptr, ptr, None, None) == -1
+    assert b"pecc_accept" in L.pecc_last_error()
