@@ -30,6 +30,8 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, TFLOP/s
+BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 matrix cores, TFLOP/s
+MLP_FLOPS_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)   # multiply-adds of the 8-64-64-1 network
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
@@ -49,6 +51,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-instance path")
     ap.add_argument("--no-restarts", action="store_true", help="skip the batched restart workload")
     ap.add_argument("--no-gbo", action="store_true", help="skip the geometric batch workload")
+    ap.add_argument("--no-lp", action="store_true", help="skip the learned-proposal workload")
+    ap.add_argument("--lp-restarts", type=int, default=20000, help="restarts of training data")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
     return ap.parse_args()
@@ -314,6 +318,87 @@ def main():
             print(f"[bench] gbo {tag}: {np.mean(ts):.1f} ms", file=sys.stderr, flush=True)
         line["gbo"] = {"workload": "64 random starts, n=1000, R=34.4, 4 x 4 blocks (~64 circles per batch)",
                        **gbo}
+
+    # ---- learned proposal: 128 x n=1000, R=34.4, 4096 candidates ----------
+    if not a.no_lp:
+        from paper_2303_02650_amd import proposal as PR
+        t0 = time.perf_counter()
+        F, Y, st = PR.generate_samples(a.lp_restarts, R_range=(34.3, 34.6), seed=1)
+        torch.cuda.synchronize()
+        t_gen = time.perf_counter() - t0
+        print(f"[bench] lp: {F.shape[0]} samples from {st['restarts']} restarts in {t_gen:.1f} s",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        scorer, hist = PR.train(F, Y, epochs=16, batch_rows=8192, lr=2e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        # kernel timings at the evaluation shape on one converged state
+        c5 = synth.C5(128)
+        B5, C5c, k5 = c5.B, 4096, 50
+        b5 = PR._Batch(1000, c5.R, torch.from_numpy(c5.xy.reshape(-1)).to(dev), PR.ssed_params())
+        e5 = b5.descend(b5.xy)
+        cc, cd = PR.draw_candidates(np.random.default_rng(7), np.full(B5, 1000), c5.R, C5c)
+        ccd, cdd = torch.from_numpy(cc.reshape(-1)).to(dev), torch.from_numpy(cd.reshape(-1)).to(dev)
+        feats = torch.empty(B5 * C5c, 8, dtype=torch.float32, device=dev)
+        logits = torch.empty(B5 * C5c, dtype=torch.float32, device=dev)
+        xy_new = torch.empty_like(b5.xy)
+        sel = torch.empty(B5, k5, dtype=torch.int32, device=dev)
+        rows = B5 * C5c
+        stages = {
+            "features": lambda: P.pecc_features(b5.inst, b5.xy, C5c, ccd, cdd, feats),
+            "mlp_forward": lambda: P.pecc_mlp_forward(scorer, feats, rows, logits),
+            "propose": lambda: P.pecc_propose(b5.inst, b5.xy, C5c, ccd, cdd, logits, k5, sel, xy_new),
+        }
+        tms = {}
+        for name, fn in stages.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tms[name] = e0.elapsed_time(e1) / reps
+        xs = xy_new.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        e_new = b5.descend(xs)
+        acc = P.accept(b5.inst, b5.xy.clone(), e5.clone(), xs, e_new)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tms["descend_verify_accept"] = e0.elapsed_time(e1)
+        T = P.MlpTrainer(scorer, max_rows=8192)
+        xb8, yb8 = F[:8192].contiguous(), Y[:8192].contiguous()
+        T.train_step(xb8, yb8)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(20):
+            T.train_step(xb8, yb8)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_step = e0.elapsed_time(e1) / 20
+        cmp = PR.compare(scorer, R=34.4, instances=128, budget=16, seed=6, xy0=c5.xy).summary()
+        fwd_tf = MLP_FLOPS_PER_ROW * rows / (tms["mlp_forward"] / 1e3) / 1e12
+        line["learned_proposal"] = {
+            "workload": "128 x n=1000, R=34.4 (seed 5), 4096 candidates per instance, top-50 "
+                        "distinct; training data from random relocations of converged "
+                        "n=1000 layouts, R in [34.3, 34.6]",
+            "training_samples": int(F.shape[0]), "training_label_mean": float(Y.mean().item()),
+            "sample_generation_s": t_gen, "restarts_per_s": st["restarts"] / t_gen,
+            "training_s": t_train, "training_loss_per_epoch": hist,
+            "train_step_ms_8192_rows": t_step, "train_rows_per_s": 8192 / (t_step / 1e3),
+            "ssed_step_ms": tms, "candidates_scored_per_s": rows / ((tms["features"] + tms["mlp_forward"]) / 1e3),
+            "roofline_mlp_forward": {"kernel": "mlp_forward_kernel", "bound": "mfma",
+                                     "achieved": fwd_tf, "peak": BF16_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": fwd_tf / BF16_PEAK_TFLOPS,
+                                     "traffic": None, "per_launch_flops": MLP_FLOPS_PER_ROW * rows,
+                                     "avg_launch_ms": tms["mlp_forward"]},
+            "vs_random": cmp}
+        print(f"[bench] lp: train {t_train:.1f} s, stages {tms}, vs random {cmp}", file=sys.stderr,
+              flush=True)
+        del F, Y
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:

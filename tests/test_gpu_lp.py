@@ -248,3 +248,30 @@ def test_accept_keeps_lower_energy(P):
     o = inst.offset
     assert np.array_equal(out[o[0]:o[1]], inst.instance(0) + 1.0)
     assert np.array_equal(out[o[1]:], inst.xy[o[1]:])
+
+
+# ---------------------------------------------------------------------------
+# The trained proposal against random proposals (statistical; parity unpinned)
+# ---------------------------------------------------------------------------
+def test_paired_arms_without_network_are_identical(P):
+    from paper_2303_02650_amd import proposal as PR
+    inst = synth.C5(16)
+    s = PR.compare(None, R=34.4, instances=16, budget=3, seed=9, xy0=inst.xy).summary()
+    assert s["mean_saving"] == 0.0 and s["learned_better"] == s["random_better"] == 0
+
+
+def test_learned_proposal_needs_fewer_descents_than_random(P):
+    """Trained on accept/reject outcomes of random relocations of converged
+    n = 1000 layouts (R in [34.3, 34.6]), evaluated on 128 fresh instances at
+    R = 34.4: descents until the first FP64-feasible layout, paired against
+    random proposals drawn from the same candidates."""
+    from paper_2303_02650_amd import proposal as PR
+    F, Y, st = PR.generate_samples(20000, R_range=(34.3, 34.6), seed=1)
+    assert F.shape[0] >= 20000 * 50 and 0.2 < Y.mean().item() < 0.8
+    scorer, hist = PR.train(F, Y, epochs=16)
+    assert hist[-1] < hist[0]
+    s = PR.compare(scorer, R=34.4, instances=128, budget=16, seed=6,
+                   xy0=synth.C5(128).xy).summary()
+    print(s)
+    assert s["mean_saving"] > 0 and s["saving_ci95"][0] > 0, s
+    assert s["feasible_learned"] >= s["feasible_random"], s
