@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, TFLOP/s
 BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 matrix cores, TFLOP/s
 MLP_FLOPS_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)   # multiply-adds of the 8-64-64-1 network
+COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
@@ -409,7 +410,7 @@ def main():
         row, col = P.build_neighbors(dbig, xb, 2.3, 0.0, True)
         E = torch.empty(dbig.B, dtype=torch.float32, device=dev)
         g = torch.empty_like(xb)
-        for _ in range(3):
+        for _ in range(5):      # first touches of the fresh output buffers are slower
             P.pecc_energy_grad(dbig, xb, row, col, col.numel(), 1.0, E, g)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -422,9 +423,23 @@ def main():
         tn = dbig.total_n
         bytes_alg = 8 * tn + 8 * tn + 4 * (tn + dbig.B) + 4 * col.numel() + 4 * dbig.B
         gbs = bytes_alg / t / 1e9
+        # plain device copy of a known size: measured copy bandwidth, and the
+        # reference dispatch that scales the profiler's byte counters
+        cal_src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        cal_dst = torch.empty_like(cal_src)
+        cal_dst.copy_(cal_src)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            cal_dst.copy_(cal_src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_gbs = 2 * COPY_BYTES / (e0.elapsed_time(e1) / 5 / 1e3) / 1e9
+        del cal_src, cal_dst
         line["roofline_sweep"] = {
             "kernel": "energy_grad_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "copy_GBs_measured": copy_gbs,
             "per_launch_bytes": bytes_alg, "avg_launch_ms": t * 1e3,
             "instances": dbig.B, "listed_pairs": int(col.numel() // 2),
             "pair_evals_per_s": (col.numel() // 2) / t}

@@ -188,14 +188,15 @@ __global__ __launch_bounds__(kBuildBlock) void build_fill_kernel(
 // ---------------------------------------------------------------------------
 // Energy and gradient over a full CSR list (Def. 3.1, Def. 3.2).  Each
 // thread owns circles and sums their pair terms in list order: no atomics.
-// One workgroup of 512 threads per instance; positions (8 KB) and the
-// instance's list segment (when it fits, 24 KB) are staged in LDS with
-// coalesced streaming (non-temporal) loads, so global memory sees each byte
-// once, and the gradient leaves with streaming stores.  Four workgroups
-// (32 waves) stay resident per CU, overlapping one instance's loads with
-// another's arithmetic.
+// One workgroup of 256 threads per instance; positions (8 KB) and the
+// instance's list segment (when it fits, 6144 entries) are staged in LDS with
+// coalesced streaming (non-temporal) 16-byte loads, the segment converted to
+// 16-bit local indices (12 KB), so global memory sees each byte once, and the
+// gradient leaves with streaming 8-byte stores.  About 20 KB of LDS per
+// workgroup keeps eight workgroups (32 waves) resident per CU, overlapping one
+// instance's loads with another's arithmetic.
 // ---------------------------------------------------------------------------
-constexpr int kSweepBlock = 512;
+constexpr int kSweepBlock = 256;
 constexpr int kColLds = 6144;
 
 __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
     float *__restrict__ energy, float *__restrict__ grad)
 {
     __shared__ float2 pos[kMaxN];
-    __shared__ int32_t col_s[kColLds];
+    __shared__ uint16_t col_s[kColLds];
     __shared__ float sum_tmp[kSweepBlock / kWave];
 
     const int b = blockIdx.x;
@@ -237,14 +238,29 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         stage_positions<kSweepBlock>(xy, off, n, pos);
     }
     if (staged) {
-#pragma unroll 4
-        for (int k = threadIdx.x; k < len; k += kSweepBlock)
-            col_s[k] = __builtin_nontemporal_load(&col[r0 + k]);
+        auto put = [&](int k, int v) {
+            const int jj = v - off;
+            col_s[k] = (unsigned)jj < (unsigned)n ? (uint16_t)jj : (uint16_t)0xFFFF;
+        };
+        const int mis = (int)((reinterpret_cast<uintptr_t>(col + r0) & 15) >> 2);
+        const int head = min(len, (4 - mis) & 3);
+        const int nv = (len - head) >> 2;
+        if ((int)threadIdx.x < head) put(threadIdx.x, col[r0 + threadIdx.x]);
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const v4i *src4 = reinterpret_cast<const v4i *>(col + r0 + head);
+#pragma unroll 2
+        for (int v = threadIdx.x; v < nv; v += kSweepBlock) {
+            const v4i t = __builtin_nontemporal_load(&src4[v]);
+            const int k = head + 4 * v;
+            put(k, t.x); put(k + 1, t.y); put(k + 2, t.z); put(k + 3, t.w);
+        }
+        for (int k = head + 4 * nv + threadIdx.x; k < len; k += kSweepBlock) put(k, col[r0 + k]);
     }
     __syncthreads();
     const float Rb = R[b];
     const float two_r = 2.0f * rad, four_r2 = two_r * two_r;
     float e = 0.0f;
+    const bool g_al = (reinterpret_cast<uintptr_t>(grad) & 7) == 0;
     for (int i = threadIdx.x; i < n; i += kSweepBlock) {
         const float2 pi = pos[i];
         int a = row[off + i] - r0, z = row[off + i + 1] - r0;
@@ -252,7 +268,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         z = z > len ? len : z;
         float gx = 0.0f, gy = 0.0f, ei = 0.0f;
         for (int k = a; k < z; ++k) {
-            const int j = (staged ? col_s[k] : col[r0 + k]) - off;
+            const int j = staged ? (int)col_s[k] : col[r0 + k] - off;
             if ((unsigned)j >= (unsigned)n) continue;   // entry outside the instance
             const float2 pj = pos[j];
             const float dx = pi.x - pj.x, dy = pi.y - pj.y;
@@ -277,8 +293,14 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         if (!(isfinite(pi.x) && isfinite(pi.y))) ei = __builtin_nanf("");
         e += ei;
         if (grad) {
-            __builtin_nontemporal_store(gx, &grad[2 * (int64_t)(off + i)]);
-            __builtin_nontemporal_store(gy, &grad[2 * (int64_t)(off + i) + 1]);
+            if (g_al) {
+                typedef float v2f __attribute__((ext_vector_type(2)));
+                const v2f t = {gx, gy};
+                __builtin_nontemporal_store(t, reinterpret_cast<v2f *>(grad) + (off + i));
+            } else {
+                __builtin_nontemporal_store(gx, &grad[2 * (int64_t)(off + i)]);
+                __builtin_nontemporal_store(gy, &grad[2 * (int64_t)(off + i) + 1]);
+            }
         }
     }
     const float tot = block_sum<kSweepBlock>(e, sum_tmp);
