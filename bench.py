@@ -247,9 +247,19 @@ def main():
         rf = torch.empty(dr.B, dtype=torch.int32, device=dev)
         re64 = torch.empty(dr.B, dtype=torch.float64, device=dev)
 
+        # measured choice of list cutoff / rebuild distance / cell side on a
+        # 64-instance sample of the workload (same outcomes, different cost)
+        from dataclasses import replace
+        from paper_2303_02650_amd import autotune as AT
+        tune = AT.tune_descent(rs.offset, rs.R, rs.xy, params, sample=64, reps=2)
+        tb = tune["best"]
+        Pr = replace(params, cutoff=tb["cutoff"], skin_half=tb["skin_half"],
+                     cell_size=tb["cell_size"]).c()
+        print(f"[bench] restarts autotune: {tb}", file=sys.stderr, flush=True)
+
         def restart_once():
             rx.copy_(r0)
-            P.pecc_lbfgs_descend(dr, rx, Pc, rout, rws)
+            P.pecc_lbfgs_descend(dr, rx, Pr, rout, rws)
             P.pecc_verify(dr, rx, 1e-20, re64, None, None, rf)
 
         restart_once()
@@ -273,7 +283,9 @@ def main():
             "pair_evals_per_s": float(rr["pair_evals"].sum()) / (rms / 1e3),
             "feasible_fraction": float(rf.cpu().numpy().mean()),
             "status_counts": {P.STATUS[s]: int((rr["status"] == s).sum()) for s in np.unique(rr["status"])},
-            "iters_mean": float(rr["iters"].mean()), "iters_max": int(rr["iters"].max())}
+            "iters_mean": float(rr["iters"].mean()), "iters_max": int(rr["iters"].max()),
+            "autotune": {"chosen": {k: tb[k] for k in ("cutoff", "skin_half", "cell_size")},
+                         "sample_instances": tune["instances"], "table": tune["table"]}}
         print(f"[bench] restarts: {rms:.2f} ms/step", file=sys.stderr, flush=True)
 
     # ---- geometric batch descent: 64 x n=1000, R=34.4, 4 x 4 blocks -------
@@ -286,20 +298,25 @@ def main():
         gout = torch.empty(dg.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
         gf = torch.empty(dg.B, dtype=torch.int32, device=dev)
         ge = torch.empty(dg.B, dtype=torch.float64, device=dev)
-        gbo = {}
+        from paper_2303_02650_amd import autotune as AT
+        gtune = AT.tune_gbo(c4.offset, c4.R, c4.xy, descent_params(P, a.max_iter), sample=16)
+        gblocks = int(gtune["best"]["blocks"])
+        gws = torch.empty(P.pecc_gbo_descend_workspace_size(dg, gblocks), dtype=torch.uint8, device=dev)
+        print(f"[bench] gbo autotune: {gtune['best']}", file=sys.stderr, flush=True)
+        gbo = {"autotune": {"chosen_blocks": gblocks, "table": gtune["table"]}}
         for tag, margin, fp64 in (("fp32", 1e-4, 0), ("fp32_margin0", 0.0, 0), ("fp64sweep_margin0", 0.0, 1)):
             gp = descent_params(P, a.max_iter)
             gp.contact_margin = margin
             gpc = gp.c()
             gx.copy_(g0)
-            P.pecc_gbo_descend(dg, gx, gpc, 4, fp64, gout, gws)      # warm-up
+            P.pecc_gbo_descend(dg, gx, gpc, gblocks, fp64, gout, gws)      # warm-up
             torch.cuda.synchronize()
             ts = []
             for _ in range(max(1, min(a.steps, 3))):
                 gx.copy_(g0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                P.pecc_gbo_descend(dg, gx, gpc, 4, fp64, gout, gws)
+                P.pecc_gbo_descend(dg, gx, gpc, gblocks, fp64, gout, gws)
                 e1.record(stream)
                 P.pecc_verify(dg, gx, 1e-20, ge, None, None, gf)
                 torch.cuda.synchronize()
@@ -317,7 +334,27 @@ def main():
                 ent["reported_E_rel_err_vs_fp64_max"] = float(rel[e64 > 0].max()) if (e64 > 0).any() else 0.0
             gbo[tag] = ent
             print(f"[bench] gbo {tag}: {np.mean(ts):.1f} ms", file=sys.stderr, flush=True)
-        line["gbo"] = {"workload": "64 random starts, n=1000, R=34.4, 4 x 4 blocks (~64 circles per batch)",
+        # the whole-instance descent on the same 64 instances, for comparison
+        wws = torch.empty(P.pecc_lbfgs_descend_workspace_size(dg), dtype=torch.uint8, device=dev)
+        wp = descent_params(P, a.max_iter).c()
+        gx.copy_(g0)
+        P.pecc_lbfgs_descend(dg, gx, wp, gout, wws)
+        torch.cuda.synchronize()
+        gx.copy_(g0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.pecc_lbfgs_descend(dg, gx, wp, gout, wws)
+        e1.record(stream)
+        P.pecc_verify(dg, gx, 1e-20, ge, None, None, gf)
+        torch.cuda.synchronize()
+        wr = P.results(gout)
+        gbo["lbfgs_whole_instance"] = {
+            "descents_per_s": dg.B / (e0.elapsed_time(e1) / 1e3), "kernel_ms": e0.elapsed_time(e1),
+            "feasible_fraction": float(gf.cpu().numpy().mean()),
+            "iters_mean": float(wr["iters"].mean()),
+            "E64_median": float(np.median(ge.cpu().numpy()))}
+        line["gbo"] = {"workload": f"64 random starts, n=1000, R=34.4, {gblocks} x {gblocks} blocks "
+                                   f"(~{1000 // (gblocks * gblocks)} circles per batch)",
                        **gbo}
 
     # ---- learned proposal: 128 x n=1000, R=34.4, 4096 candidates ----------
@@ -403,6 +440,7 @@ def main():
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:
+        torch.cuda.empty_cache()          # fresh allocations for the 2.5 GB of sweep buffers
         reps = a.sweep_batch // a.batch
         big = synth.pack([inst.instance(b) for b in range(a.batch)] * reps, list(inst.R) * reps)
         dbig = P.DeviceInstances.from_host(big.offset, big.R)
