@@ -33,6 +33,11 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, TFLOP/s
 BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 matrix cores, TFLOP/s
 MLP_FLOPS_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)   # multiply-adds of the 8-64-64-1 network
 COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
+# HBM bytes per launch of energy_grad_kernel at 65536 x n=1000, from two
+# rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
+# measured on the 1 GiB copy): profiles/energy_grad_kernel_traffic_65536x1000.md.
+# Valid for the kernel as profiled; None for other batch sizes.
+SWEEP_TRAFFIC_BYTES_65536 = 2.6011e9
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
@@ -476,7 +481,8 @@ def main():
         del cal_src, cal_dst
         line["roofline_sweep"] = {
             "kernel": "energy_grad_kernel", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": SWEEP_TRAFFIC_BYTES_65536 if dbig.B == 65536 else None,
             "copy_GBs_measured": copy_gbs,
             "per_launch_bytes": bytes_alg, "avg_launch_ms": t * 1e3,
             "instances": dbig.B, "listed_pairs": int(col.numel() // 2),
