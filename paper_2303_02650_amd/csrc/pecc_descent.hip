@@ -380,45 +380,51 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (it >= A.max_iter) { status = 5; break; }
 
             // ================= direction: two-loop recursion on B ===============
-            // lane l plays basis vector l (column l of B in registers); dl is
-            // its coefficient in H g.
+            // Lane l holds row l of B (the basis s_0..s_9, y_0..y_9, g), so
+            // acc = (B c) for the current coefficient vector c is one FMA per
+            // lane per step: q = g - sum_i a_i y_i gives acc -= a_j B[l][y_j],
+            // r = gamma q + sum_j (a_j - b_j) s_j gives acc += (a_j - b_j) B[l][s_j].
+            // s_j'q and y_j'r are then single lanes of acc (one readlane per
+            // step), and the coefficients of H g come out as scalars.
             float Bc[kNB];
 #pragma unroll
             for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
-            float dl = lane == kG ? 1.f : 0.f;
             float alph[kMM], rhoj[kMM];
 #pragma unroll
-            for (int j = kMM - 1; j >= 0; --j) {
+            for (int j = 0; j < kMM; ++j) {
                 alph[j] = 0.f;
-                rhoj[j] = 0.f;
+                rhoj[j] = j >= kMM - k ? 1.f / lane_value(Bc[kMM + j], j) : 0.f;   // 1 / s_j'y_j
+            }
+            float acc = Bc[kG];                                   // (B q)_l with q = g
+#pragma unroll
+            for (int j = kMM - 1; j >= 0; --j) {
                 if (j >= kMM - k) {
-                    rhoj[j] = 1.f / lane_value(Bc[j], kMM + j);          // 1 / s_j'y_j
-                    const float a = rhoj[j] * wave_sum_dpp(dl * Bc[j]);
+                    const float a = rhoj[j] * lane_value(acc, j);        // rho_j s_j'q
                     alph[j] = a;
-                    if (lane == kMM + j) dl -= a;
+                    acc -= a * Bc[kMM + j];
                 }
             }
+            float gam = 1.f;
             if (k > 0) {
                 const float sy = lane_value(Bc[kMM - 1], 2 * kMM - 1);
                 const float yy = lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
-                dl *= sy / yy;
+                gam = sy / yy;
             }
+            acc *= gam;                                           // (B r)_l with r = gamma q
+            float cs[kMM], cy[kMM];
 #pragma unroll
             for (int j = 0; j < kMM; ++j) {
+                cy[j] = -gam * alph[j];
+                cs[j] = 0.f;
                 if (j >= kMM - k) {
-                    const float bb = rhoj[j] * wave_sum_dpp(dl * Bc[kMM + j]);
-                    if (lane == j) dl += alph[j] - bb;
+                    const float c = alph[j] - rhoj[j] * lane_value(acc, kMM + j);   // a_j - rho_j y_j'r
+                    cs[j] = c;
+                    acc += c * Bc[j];
                 }
             }
             {
-                gp = -wave_sum_dpp(dl * Bc[kG]);
-                const float cg = lane_value(dl, kG);
-                float cs[kMM], cy[kMM];
-#pragma unroll
-                for (int j = 0; j < kMM; ++j) {
-                    cs[j] = lane_value(dl, j);
-                    cy[j] = lane_value(dl, kMM + j);
-                }
+                gp = -lane_value(acc, kG);                        // g'p = -g'r
+                const float cg = gam;
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     float px = -cg * g[c].x, py = -cg * g[c].y;
