@@ -385,22 +385,23 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // lane per step: q = g - sum_i a_i y_i gives acc -= a_j B[l][y_j],
             // r = gamma q + sum_j (a_j - b_j) s_j gives acc += (a_j - b_j) B[l][s_j].
             // s_j'q and y_j'r are then single lanes of acc (one readlane per
-            // step), and the coefficients of H g come out as scalars.
+            // step).  The per-pair scalars stay lane-indexed in VGPRs (lane j:
+            // rho_j, a_j, the s_j coefficient; lane 10 + j: rho_j and a_j again)
+            // and are read out only where the direction is formed.
             float Bc[kNB];
 #pragma unroll
             for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
-            float alph[kMM], rhoj[kMM];
-#pragma unroll
-            for (int j = 0; j < kMM; ++j) {
-                alph[j] = 0.f;
-                rhoj[j] = j >= kMM - k ? 1.f / lane_value(Bc[kMM + j], j) : 0.f;   // 1 / s_j'y_j
-            }
+            const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
+            const bool live = lane < 2 * kMM && jp >= kMM - k;
+            const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
+            const float rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
             float acc = Bc[kG];                                   // (B q)_l with q = g
+            float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
 #pragma unroll
             for (int j = kMM - 1; j >= 0; --j) {
                 if (j >= kMM - k) {
-                    const float a = rhoj[j] * lane_value(acc, j);        // rho_j s_j'q
-                    alph[j] = a;
+                    const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
+                    if (jp == j) alph_v = a;
                     acc -= a * Bc[kMM + j];
                 }
             }
@@ -411,27 +412,26 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 gam = sy / yy;
             }
             acc *= gam;                                           // (B r)_l with r = gamma q
-            float cs[kMM], cy[kMM];
+            float cs_v = 0.f;                                     // coefficient of s_j at lane j
 #pragma unroll
             for (int j = 0; j < kMM; ++j) {
-                cy[j] = -gam * alph[j];
-                cs[j] = 0.f;
                 if (j >= kMM - k) {
-                    const float c = alph[j] - rhoj[j] * lane_value(acc, kMM + j);   // a_j - rho_j y_j'r
-                    cs[j] = c;
+                    const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
+                    if (lane == j) cs_v = c;
                     acc += c * Bc[j];
                 }
             }
             {
                 gp = -lane_value(acc, kG);                        // g'p = -g'r
-                const float cg = gam;
+                const float cy_v = -gam * alph_v;                 // coefficient of y_j at lane j
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
-                    float px = -cg * g[c].x, py = -cg * g[c].y;
+                    float px = -gam * g[c].x, py = -gam * g[c].y;
 #pragma unroll
                     for (int j = 0; j < kMM; ++j) {
-                        px -= cs[j] * S[j][c].x + cy[j] * Y[j][c].x;
-                        py -= cs[j] * S[j][c].y + cy[j] * Y[j][c].y;
+                        const float csj = lane_value(cs_v, j), cyj = lane_value(cy_v, j);
+                        px -= csj * S[j][c].x + cyj * Y[j][c].x;
+                        py -= csj * S[j][c].y + cyj * Y[j][c].y;
                     }
                     p[c] = make_float2(px, py);
                 }
