@@ -127,6 +127,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; }
 
         for (;;) {
+            // Per-iteration opaque copies of the thread and lane ids: lane
+            // predicates and LDS addresses are then recomputed inside the loop
+            // (one VALU op each) instead of being hoisted and kept live as
+            // dozens of SGPR masks and VGPR addresses, which spilled.
+            int tid_l = (int)threadIdx.x;
+            asm volatile("" : "+v"(tid_l));
+            const int tid = tid_l, lane = tid_l & (kWave - 1);
             // ================= one evaluation ==================================
             float2 xt[kCPT], sc[kCPT];
             const int par = tcount & 1;
