@@ -207,32 +207,64 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) pair_mine += half_mine[c];
             // ---- pair sweep: energy and gradient of this thread's circles ----
+            // Both circles of the thread walk their lists in one loop, so their
+            // list and position reads overlap; each circle still adds its
+            // terms in list order.
             float e = 0.f, e1 = 0.f;
             double eo = 0.0, et = 0.0;
             float2 gt[kCPT], yc[kCPT];
+            float ecA[kCPT], e1cA[kCPT], gxA[kCPT], gyA[kCPT];
+            double eocA[kCPT], etcA[kCPT];
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) {
+                ecA[c] = e1cA[c] = gxA[c] = gyA[c] = 0.f;
+                eocA[c] = etcA[c] = 0.0;
+            }
+            if (!overflow) {
+                int mc[kCPT];
+                int mm = 0;
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    mc[c] = act[c] ? sh.list_n[tid + c * kDB] : 0;
+                    mm = mc[c] > mm ? mc[c] : mm;
+                }
+                for (int t = 0; t < mm; ++t) {
+                    int jv[kCPT];
+                    float2 pj[kCPT];
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        const int i = tid + c * kDB;
+                        jv[c] = t < mc[c] ? (int)sh.list[t][i] : i;
+                    }
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) pj[c] = sh.pos[jv[c]];
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        const int i = tid + c * kDB;
+                        if (t < mc[c]) {
+                            const int j = jv[c];
+                            const float2 q = xt[c];
+                            pair_term32(q, pj[c], j > i, two_r, four_r2, ecA[c], e1cA[c], gxA[c], gyA[c]);
+                            // FP64 energies only where FP32 sees (nearly) an overlap:
+                            // outside a 1e-5 band the FP64 terms are zero
+                            if (fp64 && j > i) {
+                                const float dx = q.x - pj[c].x, dy = q.y - pj[c].y;
+                                if (dx * dx + dy * dy < four_r2_band)
+                                    pair_term64(q, pj[c], two_r64, four_r2_64, eocA[c], etcA[c]);
+                            }
+                        }
+                    }
+                }
+            }
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) {
                 const int i = tid + c * kDB;
                 const float2 q = xt[c];
-                float gx = 0.f, gy = 0.f;
+                float gx = gxA[c], gy = gyA[c];
                 if (act[c]) {
-                    float ec = 0.f, e1c = 0.f;
-                    double eoc = 0.0, etc = 0.0;
-                    if (!overflow) {
-                        const int mcount = sh.list_n[i];
-                        for (int t = 0; t < mcount; ++t) {
-                            const int j = sh.list[t][i];
-                            const float2 pj = sh.pos[j];
-                            pair_term32(q, pj, j > i, two_r, four_r2, ec, e1c, gx, gy);
-                            // FP64 energies only where FP32 sees (nearly) an overlap:
-                            // outside a 1e-5 band the FP64 terms are zero
-                            if (fp64 && j > i) {
-                                const float dx = q.x - pj.x, dy = q.y - pj.y;
-                                if (dx * dx + dy * dy < four_r2_band)
-                                    pair_term64(q, pj, two_r64, four_r2_64, eoc, etc);
-                            }
-                        }
-                    } else {
+                    float ec = ecA[c], e1c = e1cA[c];
+                    double eoc = eocA[c], etc = etcA[c];
+                    if (overflow) {
                         // list overflow: every circle of the 3 x 3 cells
                         const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
                         const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
