@@ -1,0 +1,114 @@
+"""HIP-graph capture of the library's calls: every replay must reproduce the
+eager result bit for bit (the kernels are deterministic), with eager work and
+synchronisations between replays."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2303_02650_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+def capture(fn):
+    side = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def test_descent_and_verify_graph_replays(P):
+    inst = synth.C2(16)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    x0 = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    x = torch.empty_like(x0)
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4).c()
+    ws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device="cuda")
+    out = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    e64 = torch.empty(d.B, dtype=torch.float64, device="cuda")
+    feas = torch.empty(d.B, dtype=torch.int32, device="cuda")
+
+    def step():
+        x.copy_(x0)
+        P.pecc_lbfgs_descend(d, x, prm, out, ws)
+        P.pecc_verify(d, x, 1e-20, e64, None, None, feas)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (x.clone(), out.clone(), e64.clone(), feas.clone())
+    g = capture(step)
+    row, col = P.build_neighbors(d, x0)
+    for rep in range(3):
+        x.zero_(); out.zero_(); e64.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref[0]) and torch.equal(out, ref[1]), rep
+        assert torch.equal(e64, ref[2]) and torch.equal(feas, ref[3]), rep
+        P.energy_grad(d, x0, row, col)            # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_proposal_step_graph_replays(P):
+    inst = synth.C2(8)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    xy = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    cc, cd = synth.candidates(inst, 2048, synth.rng_for(41))
+    ccd, cdd = torch.from_numpy(cc.reshape(-1)).cuda(), torch.from_numpy(cd.reshape(-1)).cuda()
+    params = P.init_params(3)
+    feats = torch.empty(d.B * 2048, 8, dtype=torch.float32, device="cuda")
+    logits = torch.empty(d.B * 2048, dtype=torch.float32, device="cuda")
+    xy_new = torch.empty_like(xy)
+    sel = torch.empty(d.B, 50, dtype=torch.int32, device="cuda")
+
+    def step():
+        P.pecc_features(d, xy, 2048, ccd, cdd, feats)
+        P.pecc_mlp_forward(params, feats, d.B * 2048, logits)
+        P.pecc_propose(d, xy, 2048, ccd, cdd, logits, 50, sel, xy_new)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (feats.clone(), logits.clone(), sel.clone(), xy_new.clone())
+    g = capture(step)
+    for rep in range(3):
+        feats.zero_(); logits.zero_(); sel.zero_(); xy_new.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        got = (feats, logits, sel, xy_new)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), rep
+        P.mlp_forward(params, feats[:100])           # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_train_step_graph_replays_advance_like_eager(P):
+    rng = np.random.default_rng(42)
+    x = torch.from_numpy(rng.normal(size=(4096, 8)).astype(np.float32)).cuda()
+    y = torch.from_numpy((rng.random(4096) < 0.5).astype(np.float32)).cuda()
+    p0 = P.init_params(5)
+    eager = P.MlpTrainer(p0, lr=1e-3, max_rows=4096)
+    for _ in range(3):
+        eager.train_step(x, y)
+    torch.cuda.synchronize()
+    T = P.MlpTrainer(p0, lr=1e-3, max_rows=4096)
+    g = capture(lambda: T.train_step(x, y))
+    # capturing does not run the work: the state is still the initial one
+    assert T.step.item() == 0 and torch.equal(T.params, p0)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        P.mlp_forward(T.params, x[:64])              # eager work between replays
+        torch.cuda.synchronize()
+    assert T.step.item() == 3
+    assert torch.equal(T.params, eager.params) and torch.equal(T.m, eager.m)
+    assert torch.equal(T.v, eager.v)
