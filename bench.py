@@ -37,7 +37,10 @@ COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
 # measured on the 1 GiB copy): profiles/energy_grad_kernel_traffic_65536x1000.md.
 # Valid for the kernel as profiled; None for other batch sizes.
-SWEEP_TRAFFIC_BYTES_65536 = 2.6011e9
+SWEEP_TRAFFIC_BYTES_65536 = 2.6010e9
+# HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
+# (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
+DESCENT_TRAFFIC_BYTES_256 = 4.7e6
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
@@ -195,7 +198,7 @@ def main():
     achieved_tf = flops / t_desc / 1e12
     roof = {"kernel": "lbfgs_descend_kernel", "bound": "alu", "achieved": achieved_tf,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": DESCENT_TRAFFIC_BYTES_256 if (a.batch == 256 and a.max_iter == 5000) else None,
             "per_launch_flops": flops, "avg_launch_ms": t_desc * 1e3}
 
     line = {
