@@ -15,6 +15,8 @@ arrays through ctypes.  Each function names the part of the paper it follows:
   descend            Alg. 1 with one batch, L-BFGS reading of Eq. 8-11
   gbo_descend        Alg. 1 with geometric batches (2D grid blocks, 4 colours)
   verify             Eq. 1-2 checked through E (Eq. 5) in FP64
+  container_energy   U of Eq. 12 (radius as a variable) and its gradient
+  adjust_container   Alg. 2: 35 minimisations of U with lambda halved
 
 The learned proposal of the perturbation step (Sec. 5, Alg. 5) lives in
 ``pecc_oracle_lp.c``; the network is the project's own definition:
@@ -86,6 +88,11 @@ def lib():
         L.oracle_gbo_descend.restype = C.c_int
         L.oracle_gbo_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_void_p,
                                          C.c_void_p, dp]
+        L.oracle_container_energy.restype = C.c_double
+        L.oracle_container_energy.argtypes = [C.c_int, dp, C.c_double, C.c_double, dp]
+        L.oracle_adjust_container.restype = C.c_int
+        L.oracle_adjust_container.argtypes = [C.c_int, dp, dp, C.c_void_p, C.c_double, C.c_int,
+                                              C.c_void_p]
         i64 = C.c_int64
         L.oracle_bf16_round.restype = None
         L.oracle_bf16_round.argtypes = [i64, fp, fp]
@@ -265,6 +272,40 @@ def gbo_descend(xy, R: float, params: DescentParams | None = None, blocks: int =
     if trace:
         tr = tr[:cr.outer + 1]
     return x, res, tr
+
+
+# ---------------------------------------------------------------------------
+# Container adjustment (Sec. 4.2, Eq. 12, Alg. 2)
+# ---------------------------------------------------------------------------
+class _AdjResult(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("iters", C.c_int32), ("evals", C.c_int32),
+                ("last_status", C.c_int32), ("R", C.c_double), ("E", C.c_double)]
+
+
+def container_energy(z, rad: float = 1.0, lam: float = 1e-4):
+    """(U, grad (2n+1,)) at z = [x1, y1, ..., xn, yn, R]."""
+    z, pz = _d(np.asarray(z).reshape(-1))
+    n = (z.size - 1) // 2
+    g = np.zeros(z.size, dtype=np.float64)
+    U = lib().oracle_container_energy(n, pz, float(rad), float(lam),
+                                      g.ctypes.data_as(C.POINTER(C.c_double)))
+    return U, g
+
+
+def adjust_container(xy, R: float, params: DescentParams | None = None, lambda0: float = 1e-4,
+                     rounds: int = 35):
+    """Alg. 2 in FP64.  Returns (xy_final (n, 2), R_final, result dict)."""
+    P = params or DescentParams()
+    x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
+    Rv = C.c_double(float(R))
+    cp = _Params(**asdict(P))
+    cr = _AdjResult()
+    rc = lib().oracle_adjust_container(x.shape[0], px, C.byref(Rv), C.byref(cp), float(lambda0),
+                                       int(rounds), C.byref(cr))
+    if rc != 0:
+        raise RuntimeError(f"oracle_adjust_container failed ({rc})")
+    return x, Rv.value, {"rounds": cr.rounds, "iters": cr.iters, "evals": cr.evals,
+                         "last_status": STATUS[cr.last_status], "R": cr.R, "E": cr.E}
 
 
 # ---------------------------------------------------------------------------

@@ -396,6 +396,83 @@ int oracle_descend(int n, double *xy, double R, const oracle_params *P,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins the    */
+/* variables, z = [x_1, y_1, ..., x_n, y_n, R], and the energy gets a        */
+/* penalty that pulls the container in:                                      */
+/*   U(z, lambda) = sum_{i<j} d_ij^2 + sum_i d_i0^2 + lambda R^2,            */
+/*   d_i0 = max(0, rho_i + rad - R),  dU/dR = -2 sum_i d_i0 + 2 lambda R.    */
+/* Alg. 2: lambda starts at lambda0 (1e-4) and is halved after each of        */
+/* `rounds` (35) minimisations of U; each minimisation is a fresh L-BFGS     */
+/* descent with the readings of run_descent (no FEASIBLE stop: U > 0).       */
+/* ------------------------------------------------------------------------ */
+typedef struct { int n; double rad; double lambda; } adj_ctx;
+
+static double adj_energy(void *c, const double *z, double *g)
+{
+    const adj_ctx *a = (const adj_ctx *)c;
+    const int n = a->n;
+    const double R = z[2 * n];
+    double U = oracle_energy_grad(n, z, R, a->rad, NULL, NULL, g);
+    double sum_d0 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double rho = sqrt(z[2 * i] * z[2 * i] + z[2 * i + 1] * z[2 * i + 1]);
+        const double d0 = rho + a->rad - R;
+        if (d0 > 0.0) sum_d0 += d0;
+    }
+    U += a->lambda * R * R;
+    if (g) g[2 * n] = -2.0 * sum_d0 + 2.0 * a->lambda * R;
+    return U;
+}
+
+/* U and its gradient (2n + 1 entries) at z, for tests. */
+double oracle_container_energy(int n, const double *z, double rad, double lambda, double *g)
+{
+    adj_ctx c = { n, rad, lambda };
+    return adj_energy(&c, z, g);
+}
+
+typedef struct {
+    int32_t rounds;       /* minimisations run                                */
+    int32_t iters;        /* accepted iterations over all rounds              */
+    int32_t evals;        /* energy evaluations over all rounds               */
+    int32_t last_status;  /* status of the last round's descent               */
+    double R;             /* final radius                                     */
+    double E;             /* E of the final layout at the final radius        */
+} oracle_adjust_result;
+
+int oracle_adjust_container(int n, double *xy, double *R, const oracle_params *P,
+                            double lambda0, int rounds, oracle_adjust_result *res)
+{
+    if (P->m < 1 || P->m > 64 || rounds < 0) return -2;
+    double *z = malloc(sizeof(double) * (size_t)(2 * n + 1));
+    if (!z) return -1;
+    memcpy(z, xy, sizeof(double) * 2 * (size_t)n);
+    z[2 * n] = *R;
+    oracle_params Q = *P;
+    Q.e_feasible = 0.0;                      /* U is positive: no feasible stop */
+    double lambda = lambda0;
+    memset(res, 0, sizeof(*res));
+    for (int t = 0; t < rounds; ++t) {
+        adj_ctx c = { n, P->rad, lambda };
+        oracle_result r;
+        int rc = run_descent(2 * n + 1, z, &Q, adj_energy, &c, &r, NULL);
+        if (rc != 0) { free(z); return rc; }
+        res->iters += r.iters;
+        res->evals += r.evals;
+        res->last_status = r.status;
+        res->rounds = t + 1;
+        if (r.status == OR_NONFINITE) break;
+        lambda *= 0.5;
+    }
+    memcpy(xy, z, sizeof(double) * 2 * (size_t)n);
+    *R = z[2 * n];
+    res->R = *R;
+    res->E = oracle_energy_grad(n, xy, *R, P->rad, NULL, NULL, NULL);
+    free(z);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* FP64 feasibility check (Eq. 1-2 through Eq. 5 with unit circles).         */
 /* out[0] = E, out[1] = max_{i<j} d_ij, out[2] = max_i d_i0 (both >= 0),     */
 /* returns 1 if E < tol.  Positions are FP32, promoted exactly.  A non-      */
