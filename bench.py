@@ -93,10 +93,27 @@ def _oracle_descent(args):
     return time.perf_counter() - t0, res
 
 
-def run_cpu_baseline(inst, max_iter, sample, cores):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(inst, max_iter, sample, cores, gpu_pairs_per_eval=None):
     import multiprocessing as mp
     import oracle
+    import synth
     oracle.lib()   # built before the pool forks
+    # one descent on one thread at the C1 and C2 shapes
+    single = {}
+    for tag, one in (("C1_n20", synth.C1()), ("C2_n1000", synth.C2(1))):
+        dt, res = _oracle_descent((one.instance(0), float(one.R[0]), 2000 if tag == "C1_n20" else max_iter))
+        single[tag] = {"seconds": dt, "iters": res["iters"], "status": res["status"]}
     jobs = [(inst.instance(b), float(inst.R[b]), max_iter) for b in range(sample)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
@@ -111,7 +128,12 @@ def run_cpu_baseline(inst, max_iter, sample, cores):
                        f"L-BFGS descents over {cores} processes; {iters} iterations, "
                        f"{evals} evaluations of n(n-1)/2 = {n * (n - 1) // 2} pairs; "
                        f"{feas} feasible; wall {wall:.1f} s"),
-            "pair_evals_per_s_bruteforce": evals * n * (n - 1) / 2 / wall}
+            "pair_evals_per_s_bruteforce": evals * n * (n - 1) / 2 / wall,
+            "pair_evals_per_s_list_equivalent": (evals * gpu_pairs_per_eval / wall
+                                                 if gpu_pairs_per_eval else None),
+            "list_equivalent_note": "oracle evaluations x the GPU run's mean listed pairs (i<j) per evaluation",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "single_thread_descent": single}
 
 
 def main():
@@ -211,6 +233,8 @@ def main():
                                f"max_iter={a.max_iter}, cutoff 2.3, skin 0.15",
                    "instances": a.batch, "n": N_CIRCLES, "R": R_C2},
         "pair_evals_per_s": pair_evals / (ms_per_step / 1e3),
+        "step_ms_events_median": float(np.median(np.array(desc_ms) + np.array(ver_ms))),
+        "descent_ms_events_median": float(np.median(desc_ms)),
         "feasible_fraction": float(f.mean()),
         "status_counts": status_counts,
         "iters_mean": float(res["iters"].mean()), "evals_mean": float(res["evals"].mean()),
@@ -294,6 +318,29 @@ def main():
             "iters_mean": float(rr["iters"].mean()), "iters_max": int(rr["iters"].max()),
             "autotune": {"chosen": {k: tb[k] for k in ("cutoff", "skin_half", "cell_size")},
                          "sample_instances": tune["instances"], "table": tune["table"]}}
+        if not a.no_plain:
+            # plain path on a sample of the restarts: one call per instance, no graph
+            kp = min(a.plain_sample, dr.B)
+            pl = []
+            for b in range(kp):
+                one = synth.pack([rs.instance(b)], [rs.R[b]])
+                db = P.DeviceInstances.from_host(one.offset, one.R)
+                x1 = torch.from_numpy(one.xy.reshape(-1)).to(dev)
+                pl.append((db, x1, torch.empty_like(x1),
+                           torch.empty(P.pecc_lbfgs_descend_workspace_size(db), dtype=torch.uint8, device=dev),
+                           torch.empty(P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)))
+            db, x1, xw, wsb, ob = pl[0]
+            xw.copy_(x1); P.pecc_lbfgs_descend(db, xw, Pr, ob, wsb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for db, x1, xw, wsb, ob in pl:
+                xw.copy_(x1)
+                P.pecc_lbfgs_descend(db, xw, Pr, ob, wsb)
+                torch.cuda.synchronize()
+            prate = kp / (time.perf_counter() - t0)
+            line["restarts"]["plain_descents_per_s"] = prate
+            line["restarts"]["batched_over_plain"] = line["restarts"]["descents_per_s"] / prate
+            line["restarts"]["plain_sample"] = kp
         print(f"[bench] restarts: {rms:.2f} ms/step", file=sys.stderr, flush=True)
 
     # ---- geometric batch descent: 64 x n=1000, R=34.4, 4 x 4 blocks -------
@@ -448,6 +495,32 @@ def main():
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:
+        # the C3 shape (256 random starts, n in [300, 1000]): ~5 MB, cache
+        # resident, so its rate is an effective one, not an HBM figure
+        c3 = synth.C3(256)
+        dc3 = P.DeviceInstances.from_host(c3.offset, c3.R)
+        xc3 = torch.from_numpy(c3.xy.reshape(-1)).to(dev)
+        rc3, cc3 = P.build_neighbors(dc3, xc3, 2.3, 0.0, True)
+        Ec3 = torch.empty(dc3.B, dtype=torch.float32, device=dev)
+        gc3 = torch.empty_like(xc3)
+        for _ in range(5):
+            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), 1.0, Ec3, gc3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(100):
+            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), 1.0, Ec3, gc3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t3 = e0.elapsed_time(e1) / 1e3 / 100
+        tn3 = dc3.total_n
+        b3 = 8 * tn3 + 8 * tn3 + 4 * (tn3 + dc3.B) + 4 * cc3.numel() + 4 * dc3.B
+        line["sweep_c3_effective"] = {
+            "kernel": "energy_grad_kernel", "instances": dc3.B, "circles": tn3,
+            "per_launch_bytes": b3, "avg_launch_ms": t3 * 1e3,
+            "effective_GBs": b3 / t3 / 1e9, "pair_evals_per_s": (cc3.numel() // 2) / t3,
+            "note": "cache-resident working set: an effective rate, not an HBM figure"}
+        del c3, dc3, xc3, rc3, cc3, Ec3, gc3
         torch.cuda.empty_cache()          # fresh allocations for the 2.5 GB of sweep buffers
         reps = a.sweep_batch // a.batch
         big = synth.pack([inst.instance(b) for b in range(a.batch)] * reps, list(inst.R) * reps)
@@ -500,7 +573,8 @@ def main():
         sample = min(a.cpu_sample or a.batch, a.batch)
         print(f"[bench] oracle CPU baseline: {sample} descents on {cores} processes ...",
               file=sys.stderr, flush=True)
-        line["cpu_baseline"] = run_cpu_baseline(inst, a.max_iter, sample, cores)
+        line["cpu_baseline"] = run_cpu_baseline(inst, a.max_iter, sample, cores,
+                                                gpu_pairs_per_eval=pair_evals / max(1, int(res["evals"].sum())))
 
     print(json.dumps(line), flush=True)
 
