@@ -189,15 +189,16 @@ __global__ __launch_bounds__(kBuildBlock) void build_fill_kernel(
 // Energy and gradient over a full CSR list (Def. 3.1, Def. 3.2).  Each
 // thread owns circles and sums their pair terms in list order: no atomics.
 // One workgroup of 256 threads per instance; positions (8 KB) and the
-// instance's list segment (when it fits, 6144 entries) are staged in LDS with
+// instance's list segment (when it fits, 6128 entries) are staged in LDS with
 // coalesced streaming (non-temporal) 16-byte loads, the segment converted to
-// 16-bit local indices (12 KB), so global memory sees each byte once, and the
-// gradient leaves with streaming 8-byte stores.  About 20 KB of LDS per
-// workgroup keeps eight workgroups (32 waves) resident per CU, overlapping one
-// instance's loads with another's arithmetic.
+// 16-bit local indices, so global memory sees each byte once, and the
+// gradient leaves with streaming 8-byte stores.  The LDS footprint (20,480
+// bytes) lets eight workgroups (32 waves) stay resident per CU, overlapping
+// one instance's loads with another's arithmetic, and each thread walks the
+// lists of two circles at once so that their LDS reads overlap.
 // ---------------------------------------------------------------------------
 constexpr int kSweepBlock = 256;
-constexpr int kColLds = 6144;
+constexpr int kColLds = 6128;   // 8192 + 2 * 6128 + 16 bytes of LDS fit 8 workgroups per CU
 
 __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ R,
@@ -261,27 +262,57 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
     const float two_r = 2.0f * rad, four_r2 = two_r * two_r;
     float e = 0.0f;
     const bool g_al = (reinterpret_cast<uintptr_t>(grad) & 7) == 0;
-    for (int i = threadIdx.x; i < n; i += kSweepBlock) {
-        const float2 pi = pos[i];
-        int a = row[off + i] - r0, z = row[off + i + 1] - r0;
-        a = a < 0 ? 0 : a;
-        z = z > len ? len : z;
-        float gx = 0.0f, gy = 0.0f, ei = 0.0f;
-        for (int k = a; k < z; ++k) {
-            const int j = staged ? (int)col_s[k] : col[r0 + k] - off;
-            if ((unsigned)j >= (unsigned)n) continue;   // entry outside the instance
-            const float2 pj = pos[j];
-            const float dx = pi.x - pj.x, dy = pi.y - pj.y;
-            const float l2 = dx * dx + dy * dy;
-            // branch-free: d = 0 without overlap, no gradient at l = 0
-            const bool ov = l2 < four_r2;
-            const float il = (ov && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
-            const float d = ov ? two_r - l2 * il : 0.f;
-            ei += j > i ? d * d : 0.f;
-            const float kf = -2.f * d * il;
-            gx += kf * dx;
-            gy += kf * dy;
-        }
+    for (int i0 = threadIdx.x; i0 < n; i0 += 2 * kSweepBlock) {
+      // two circles per pass (i0 and i0 + kSweepBlock): their list and
+      // position reads overlap; each keeps its own order of terms
+      float gxA[2], gyA[2], eiA[2];
+      int aA[2], zA[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+          const int i = i0 + h * kSweepBlock;
+          gxA[h] = gyA[h] = eiA[h] = 0.f;
+          aA[h] = 0; zA[h] = 0;
+          if (i < n) {
+              int a = row[off + i] - r0, z = row[off + i + 1] - r0;
+              aA[h] = a < 0 ? 0 : a;
+              zA[h] = z > len ? len : z;
+          }
+      }
+      const int span = max(zA[0] - aA[0], zA[1] - aA[1]);
+      const float2 piA[2] = {pos[i0], i0 + kSweepBlock < n ? pos[i0 + kSweepBlock] : make_float2(0.f, 0.f)};
+      for (int t = 0; t < span; ++t) {
+          int jA[2];
+          float2 pjA[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+              const int k = aA[h] + t;
+              jA[h] = k < zA[h] ? (staged ? (int)col_s[k] : col[r0 + k] - off) : -1;
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) pjA[h] = pos[(unsigned)jA[h] < (unsigned)n ? jA[h] : 0];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+              const int i = i0 + h * kSweepBlock;
+              const int j = jA[h];
+              if ((unsigned)j >= (unsigned)n) continue;   // past the row, or outside the instance
+              const float2 pi = piA[h], pj = pjA[h];
+              const float dx = pi.x - pj.x, dy = pi.y - pj.y;
+              const float l2 = dx * dx + dy * dy;
+              const bool ov = l2 < four_r2;
+              const float il = (ov && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
+              const float d = ov ? two_r - l2 * il : 0.f;
+              eiA[h] += j > i ? d * d : 0.f;
+              const float kf = -2.f * d * il;
+              gxA[h] += kf * dx;
+              gyA[h] += kf * dy;
+          }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = i0 + h * kSweepBlock;
+        if (i >= n) break;
+        const float2 pi = piA[h];
+        float gx = gxA[h], gy = gyA[h], ei = eiA[h];
         const float r2 = pi.x * pi.x + pi.y * pi.y;
         const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
         const float d0 = fmaxf(r2 * ir + rad - Rb, 0.f);
@@ -302,6 +333,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
                 __builtin_nontemporal_store(gy, &grad[2 * (int64_t)(off + i) + 1]);
             }
         }
+      }
     }
     const float tot = block_sum<kSweepBlock>(e, sum_tmp);
     if (threadIdx.x == 0) energy[b] = tot;
