@@ -18,6 +18,7 @@
 // Workgroups take instances from a queue, largest n first, until the queue
 // is empty (the launch is sized to the resident capacity of the device).
 #include "pecc_device.hpp"
+#include "pecc_host.hpp"
 #include "pecc_launch.hpp"
 #include "pecc_lbfgs.hpp"
 
@@ -550,21 +551,8 @@ __global__ __launch_bounds__(kQB) void queue_init_kernel(const int32_t *__restri
 
 int descend_grid(int B)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
-    static int per_cu = 0;
-    if (per_cu == 0) {
-        int occ = 0;
-        per_cu = (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, lbfgs_descend_kernel, kDB, 0) ==
-                      hipSuccess && occ > 0) ? occ : 1;
-    }
-    const int cap = cus * per_cu;
+    static std::atomic<int> per_cu[kMaxDevices];
+    const int cap = current_device_cus() * resident_per_cu(lbfgs_descend_kernel, kDB, per_cu);
     return B < cap ? B : cap;
 }
 

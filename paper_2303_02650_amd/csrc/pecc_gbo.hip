@@ -26,6 +26,7 @@
 // Results are bitwise reproducible: membership, list order and every sum
 // are functions of the positions only.
 #include "pecc_device.hpp"
+#include "pecc_host.hpp"
 #include "pecc_launch.hpp"
 #include "pecc_lbfgs.hpp"
 
@@ -650,14 +651,7 @@ size_t gbo_workspace_bytes(int B, int blocks)
 
 int gbo_grid(int B)
 {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
+    const int cus = current_device_cus();
     return B < cus ? B : cus;
 }
 
