@@ -210,6 +210,29 @@ int pecc_verify(const pecc_instances *inst, const float *xy, double tol,
                 double *energy64, double *max_pair_overlap, double *max_cont_overlap,
                 int32_t *feasible, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Container adjustment (Sec. 4.2, Eq. 12, Alg. 2): the radius becomes a
+ * variable and U(z, lambda) = E + lambda R^2 is minimised over z = (x, R),
+ * `rounds` times (35 in the paper) with lambda halved after each round from
+ * lambda0 (1e-4), every round a fresh L-BFGS descent with the stop rules of
+ * p (g_tol / ftol / max_iter per round; no FEASIBLE stop since U > 0 and no
+ * FP64 regime: tau64 and e_feasible are not used).  The radius component of
+ * the gradient is dU/dR = -2 sum_i d_i0 + 2 lambda R.
+ * inst->R holds the starting radii; R_out (device float [B]) receives the
+ * final ones and xy the final layouts.  out[b].iters counts iterations over
+ * all rounds, out[b].status is the last round's, out[b].E32 the energy E
+ * (circles of radius 1 + contact_margin) at the final layout and radius.
+ * FP32 positions bound the radius to about the FP32 spacing of the
+ * coordinates times a few; check feasibility of unit circles with
+ * pecc_verify at the returned radii (a contact margin leaves slack for it).
+ * Errors: as pecc_lbfgs_descend, plus lambda0 < 0 or not finite, rounds
+ * outside [0, 64], R_out NULL.
+ * ------------------------------------------------------------------------ */
+int pecc_adjust_container_workspace_size(const pecc_instances *inst, size_t *bytes);
+int pecc_adjust_container(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
+                          float lambda0, int32_t rounds, float *R_out, pecc_descent_result *out,
+                          void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ========================================================================
  * Learned proposal for the perturbation step of SED (Sec. 5, Alg. 5).
  *

@@ -80,6 +80,9 @@ _sig = {
     "pecc_gbo_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
+    "pecc_adjust_container_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
+    "pecc_adjust_container": (C.c_int, [_P(pecc_instances), _V, _P(pecc_descent_params), C.c_float,
+                                        C.c_int32, _V, _V, _V, C.c_size_t, _V]),
     "pecc_features": (C.c_int, [_P(pecc_instances), _V, C.c_int32, _V, _V, _V, _V]),
     "pecc_mlp_forward": (C.c_int, [_V, _V, C.c_int64, _V, _V]),
     "pecc_mlp_grad_workspace_size": (C.c_int, [C.c_int64, _P(C.c_size_t)]),
@@ -287,6 +290,32 @@ def gbo_descend(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams |
                                 device=xy.device)
     pecc_gbo_descend(inst, xy, P, blocks, sweep_fp64, out, workspace)
     return out
+
+
+def pecc_adjust_container_workspace_size(inst: DeviceInstances) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_adjust_container_workspace_size(C.byref(inst.c()), C.byref(b)))
+    return b.value
+
+
+def pecc_adjust_container(inst, xy, params: pecc_descent_params, lambda0, rounds, R_out, out,
+                          workspace, stream=None):
+    _check(_lib.pecc_adjust_container(C.byref(inst.c()), _ptr(xy), C.byref(params), float(lambda0),
+                                      int(rounds), _ptr(R_out), _ptr(out), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(),
+                                      _stream(stream)))
+
+
+def adjust_container(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams | None = None,
+                     lambda0: float = 1e-4, rounds: int = 35):
+    """Container adjustment (Alg. 2) in place on xy; returns (R_out float32
+    [B], device result buffer)."""
+    P = (params or DescentParams()).c()
+    out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=xy.device)
+    ws = torch.empty(pecc_adjust_container_workspace_size(inst), dtype=torch.uint8, device=xy.device)
+    R_out = torch.empty(inst.B, dtype=torch.float32, device=xy.device)
+    pecc_adjust_container(inst, xy, P, lambda0, rounds, R_out, out, ws)
+    return R_out, out
 
 
 def results(out: torch.Tensor) -> np.ndarray:

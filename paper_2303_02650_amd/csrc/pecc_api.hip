@@ -172,6 +172,8 @@ int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs
     a->skin2 = skin * skin;
     a->e_feasible = p->e_feasible;
     a->tau64 = p->tau64;
+    a->lambda0 = 0.f;
+    a->rounds = 0;
     return PECC_OK;
 }
 
@@ -197,6 +199,39 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent
     return check_hip(pecc::launch_descend(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
                                           inst->total_n, a, out, (int32_t *)workspace, grid,
                                           stream),
+                     fn);
+}
+
+int pecc_adjust_container_workspace_size(const pecc_instances *inst, size_t *bytes)
+{
+    return pecc_lbfgs_descend_workspace_size(inst, bytes);
+}
+
+int pecc_adjust_container(const pecc_instances *inst, float *xy, const pecc_descent_params *p,
+                          float lambda0, int32_t rounds, float *R_out, pecc_descent_result *out,
+                          void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    const char *fn = "pecc_adjust_container";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out || !R_out) return fail(PECC_ERR_INVALID, "%s: params, out and R_out must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    if (!(lambda0 >= 0.f && lambda0 < 1e30f))
+        return fail(PECC_ERR_INVALID, "%s: lambda0 must be finite and >= 0", fn);
+    if (rounds < 0 || rounds > 64) return fail(PECC_ERR_INVALID, "%s: rounds outside [0, 64]", fn);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
+    a.lambda0 = lambda0;
+    a.rounds = rounds;
+    size_t need = 0;
+    pecc_lbfgs_descend_workspace_size(inst, &need);
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    const int grid = pecc::descend_grid(inst->num_instances);
+    return check_hip(pecc::launch_adjust(inst->offset, inst->R, xy, inst->num_instances,
+                                         inst->total_n, a, R_out, out, (int32_t *)workspace, grid,
+                                         stream),
                      fn);
 }
 

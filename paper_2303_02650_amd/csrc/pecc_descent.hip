@@ -50,11 +50,20 @@ struct DescentShared {
 // Evaluation requests of the descent's state machine.
 enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2 };
 
+// ADJ: container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins
+// the variables, the objective is U = E + lambda R^2 and A.rounds
+// minimisations run with lambda halved after each (a fresh history every
+// round).  Lane l additionally holds the radius component of basis vector l
+// (hR_v), so after the fused reduction every Gram entry gets its R x R
+// product added, and the unit-circle energy slot carries sum_i d_i0 instead,
+// from which dU/dR = -2 sum_i d_i0 + 2 lambda R.  FP32 throughout (no FP64
+// regime, no FEASIBLE stop: U > 0); Rout[b] receives the final radius.
+template <bool ADJ>
 __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ Rv,
     const double *__restrict__ Rv64, float *__restrict__ xy,
     int B, int64_t total_n, DescentArgs A, DescentResultDev *__restrict__ out,
-    int32_t *__restrict__ queue)
+    int32_t *__restrict__ queue, float *__restrict__ Rout)
 {
     __shared__ DescentShared sh;
     const int tid = threadIdx.x;
@@ -127,6 +136,23 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
         if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; }
 
+        // container adjustment state (uniform): radius, its gradient and
+        // search components, penalty coefficient; hR_v: radius component of
+        // basis vector `lane`
+        float Rz = R, gR = 0.f, pR = 0.f, lam = ADJ ? A.lambda0 : 0.f;
+        float hR_v = 0.f;
+        int iters_all = 0;
+        for (int round = 0;; ++round) {
+        if constexpr (ADJ) {
+            if (round >= A.rounds) break;
+            // fresh minimisation of U at this lambda; every wave has left
+            // the previous round's reads of B before it is cleared
+            __syncthreads();
+            for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
+            k = 0; cur = 0; it = 0; h = 0; status = 0;
+            req = kReqInit;
+            hR_v = 0.f;
+        }
         for (;;) {
             // Per-iteration opaque copies of the thread and lane ids: lane
             // predicates and LDS addresses are then recomputed inside the loop
@@ -138,6 +164,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // ================= one evaluation ==================================
             float2 xt[kCPT], sc[kCPT];
             const int par = tcount & 1;
+            // container radius of this evaluation (a variable only when adjusting)
+            const float Rt = ADJ ? (req == kReqTrial ? fmaf(alpha, pR, Rz) : Rz) : R;
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) {
                 xt[c] = req == kReqTrial ? make_float2(fmaf(alpha, p[c].x, x[c].x), fmaf(alpha, p[c].y, x[c].y))
@@ -287,16 +315,20 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         }
                     }
                     e += ec;
-                    e1 += e1c;
+                    if constexpr (!ADJ) e1 += e1c;
                     eo += eoc;
                     et += etc;
                     // containment (branch-free, as the pair term)
                     const float r2 = q.x * q.x + q.y * q.y;
                     const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    const float d0 = fmaxf(r2 * ir + rad - R, 0.f);
+                    const float d0 = fmaxf(r2 * ir + rad - Rt, 0.f);
                     e += d0 * d0;
-                    const float d01 = fmaxf(d0 - (rad - 1.f), 0.f);
-                    e1 += d01 * d01;
+                    if constexpr (ADJ) {
+                        e1 += d0;                     // sum of d_i0: dU/dR
+                    } else {
+                        const float d01 = fmaxf(d0 - (rad - 1.f), 0.f);
+                        e1 += d01 * d01;
+                    }
                     const float kc = 2.f * d0 * ir;
                     gx += kc * q.x;
                     gy += kc * q.y;
@@ -331,6 +363,35 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (fp64) {
 #pragma unroll
                 for (int w = 0; w < kDW; ++w) { so += sh.red64[par][w][0]; st += sh.red64[par][w][1]; }
+            }
+            float gRt = 0.f, scR = 0.f, ycR = 0.f;
+            if constexpr (ADJ) {
+                // radius components of the reduced dot products: lane L holds
+                // slot L, whose operands are (trial gradient | step | change of
+                // gradient) and (a basis vector | one of those three)
+                gRt = -2.f * lane_value(tot, sE1) + 2.f * lam * Rt;     // dU/dR at the trial
+                scR = Rt - Rz;
+                ycR = gRt - gR;
+                const int L = lane;
+                int bsel = 0;
+                float uR = 0.f;
+                if (L < 2 * kMM) { bsel = L; uR = gRt; }                                   // gt . s_j, gt . y_j
+                else if (L < 3 * kMM - 1) { bsel = L - 2 * kMM + 1; uR = scR; }            // sc . s_j
+                else if (L < 4 * kMM - 2) { bsel = kMM + L - (3 * kMM - 1) + 1; uR = scR; } // sc . y_j
+                else if (L < 5 * kMM - 3) { bsel = L - (4 * kMM - 2) + 1; uR = ycR; }      // yc . s_j
+                else if (L < 6 * kMM - 4) { bsel = kMM + L - (5 * kMM - 3) + 1; uR = ycR; } // yc . y_j
+                const float vR = __builtin_bit_cast(
+                    float, __builtin_amdgcn_ds_bpermute(4 * bsel, __builtin_bit_cast(int, hR_v)));
+                float corr = uR * vR;
+                if (L == sGG) corr = gRt * gRt;
+                else if (L == sScSc) corr = scR * scR;
+                else if (L == sScYc) corr = scR * ycR;
+                else if (L == sYcYc) corr = ycR * ycR;
+                else if (L == sScG) corr = scR * gRt;
+                else if (L == sYcG) corr = ycR * gRt;
+                else if (L == sE) corr = lam * Rt * Rt;                 // U = E + lambda R^2
+                else if (L == sE1) corr = 0.f;
+                tot += corr;
             }
             const float Et = lane_value(tot, sE);
             const float E1t = lane_value(tot, sE1);
@@ -388,13 +449,26 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     g[c] = gt[c];
                 }
                 if (push) k = k + 1 > A.m ? A.m : k + 1;
+                if constexpr (ADJ) {
+                    if (push) {                 // shift the radius components like S and Y
+                        const int L = lane;
+                        const int src = (L < kMM - 1 || (L >= kMM && L < 2 * kMM - 1)) ? L + 1 : L;
+                        float v = __builtin_bit_cast(
+                            float, __builtin_amdgcn_ds_bpermute(4 * src, __builtin_bit_cast(int, hR_v)));
+                        if (L == kMM - 1) v = scR;
+                        if (L == 2 * kMM - 1) v = ycR;
+                        hR_v = v;
+                    }
+                    Rz = Rt;
+                    gR = gRt;
+                }
                 if (req == kReqTrial) ++it;
                 E = Et;
                 if (fp64) { E64o = so; E64t = st; }
                 // FP64 regime once either FP32 energy is small: with a contact
                 // margin the unit circles can be overlap-free while E (radius
                 // rad) still sums (2 mu)^2 over every contact
-                if (!fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
+                if (!ADJ && !fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
                     fp64 = true;
                     req = kReqFp64;          // FP64 energies of x before going on
                     continue;
@@ -475,17 +549,31 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     p[c] = make_float2(px, py);
                 }
+                if constexpr (ADJ) {
+                    float pr = -gam * gR;
+#pragma unroll
+                    for (int j = 0; j < kMM; ++j)
+                        pr -= lane_value(cs_v, j) * lane_value(hR_v, j) +
+                              lane_value(cy_v, j) * lane_value(hR_v, kMM + j);
+                    pR = pr;
+                }
             }
             if (k > 0 && !(gp < 0.f)) {
                 k = 0;
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) p[c] = make_float2(-g[c].x, -g[c].y);
+                if constexpr (ADJ) pR = -gR;
                 gp = -gg;
             }
             alpha = k > 0 ? 1.f : 1.f / fmaxf(1.f, gn);
             h = 0;
             req = kReqTrial;
         }
+        iters_all += it;
+        if constexpr (!ADJ) break;
+        if (status == 6) break;                  // NONFINITE ends the adjustment
+        lam *= 0.5f;
+        }   // rounds
 
         // ---- write back ------------------------------------------------------
         {
@@ -507,14 +595,17 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         if (tid == 0) {
             DescentResultDev r;
             r.status = status;
-            r.iters = it;
+            r.iters = iters_all;
             r.evals = evals;
             r.rebuilds = rebuilds;
             r.pair_evals = pair_mine;
-            r.E32 = E;
+            // with the radius as a variable, E reports the energy without
+            // the penalty (the last lambda was halved once more after the round)
+            r.E32 = (ADJ && A.rounds > 0) ? E - 2.f * lam * Rz * Rz : E;
             r.gnorm = sqrtf(fmaxf(sh.Bm[cur][kG * kNB + kG], 0.f));
             r.E64 = fp64 ? E64t : -1.0;
             out[b] = r;
+            if constexpr (ADJ) Rout[b] = Rz;
         }
     }
 }
@@ -552,7 +643,7 @@ __global__ __launch_bounds__(kQB) void queue_init_kernel(const int32_t *__restri
 int descend_grid(int B)
 {
     static std::atomic<int> per_cu[kMaxDevices];
-    const int cap = current_device_cus() * resident_per_cu(lbfgs_descend_kernel, kDB, per_cu);
+    const int cap = current_device_cus() * resident_per_cu(lbfgs_descend_kernel<false>, kDB, per_cu);
     return B < cap ? B : cap;
 }
 
@@ -568,8 +659,21 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
 {
     queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
     if (grid < 1) grid = 1;
-    lbfgs_descend_kernel<<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
-                                              reinterpret_cast<DescentResultDev *>(out), queue);
+    lbfgs_descend_kernel<false><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
+                                                     reinterpret_cast<DescentResultDev *>(out),
+                                                     queue, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B,
+                         int64_t total_n, const DescentArgs &a, float *Rout, void *out,
+                         int32_t *queue, int grid, hipStream_t s)
+{
+    queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
+    if (grid < 1) grid = 1;
+    lbfgs_descend_kernel<true><<<grid, kDB, 0, s>>>(offset, R, nullptr, xy, B, total_n, a,
+                                                    reinterpret_cast<DescentResultDev *>(out),
+                                                    queue, Rout);
     return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ struct DescentArgs {
     int m, max_iter, max_halvings, ftol_window;
     float c1, eps_curv, h_req, g_tol, ftol, rad;
     double c2, skin2, e_feasible, tau64;
+    float lambda0;    // container adjustment: first penalty coefficient
+    int rounds;       // container adjustment: minimisations, lambda halved after each
 };
 
 struct DescentResultDev;  // layout-identical to pecc_descent_result
@@ -33,6 +35,12 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
                           int32_t *queue, int grid, hipStream_t s);
 
 int descend_grid(int B);   // persistent workgroups to launch for B instances
+
+// Container adjustment: the descent with the radius as a variable (Rout[B]
+// receives the final radii; the initial ones come from R).
+hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B,
+                         int64_t total_n, const DescentArgs &a, float *Rout, void *out,
+                         int32_t *queue, int grid, hipStream_t s);
 
 // Geometric batch descent: workspace bytes and launch.
 size_t gbo_workspace_bytes(int B, int blocks);

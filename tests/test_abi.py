@@ -146,3 +146,21 @@ def test_learned_proposal_entry_points_reject_bad_arguments(P):
     assert L.pecc_propose(C.byref(inst), ptr, 4, ptr, ptr, None, 3, ptr, None, None) == -1
     assert L.pecc_accept(C.byref(inst), ptr, None, ptr, ptr, None, None) == -1
     assert b"pecc_accept" in L.pecc_last_error()
+
+
+def test_adjust_container_rejects_bad_arguments(P):
+    inst = _fake_inst(P)
+    ptr = C.c_void_p(0x5000)
+    prm = P.default_params().c()
+    L = P._lib
+    b = C.c_size_t()
+    assert L.pecc_adjust_container_workspace_size(C.byref(inst), C.byref(b)) == 0
+    args = lambda lam, rounds, rout: (C.byref(inst), ptr, C.byref(prm), lam, rounds, rout, ptr, ptr,
+                                      b.value, None)
+    assert L.pecc_adjust_container(*args(-1.0, 35, ptr)) == -1
+    assert L.pecc_adjust_container(*args(float("nan"), 35, ptr)) == -1
+    assert L.pecc_adjust_container(*args(1e-4, 65, ptr)) == -1
+    assert L.pecc_adjust_container(*args(1e-4, -1, ptr)) == -1
+    assert L.pecc_adjust_container(*args(1e-4, 35, None)) == -1
+    assert L.pecc_adjust_container(C.byref(inst), ptr, C.byref(prm), 1e-4, 35, ptr, ptr, ptr,
+                                   b.value - 1, None) == -2
