@@ -18,6 +18,10 @@ arrays through ctypes.  Each function names the part of the paper it follows:
   container_energy   U of Eq. 12 (radius as a variable) and its gradient
   adjust_container   Alg. 2: 35 minimisations of U with lambda halved
 
+The solution-space exploring and descent heuristic (Sec. 5, Alg. 5) lives in
+``pecc_oracle_sed.c``: philox (Philox4x64-10), sed_shift / sed_perturb,
+sed_uniform, sed_J, sed_select, sed.
+
 The learned proposal of the perturbation step (Sec. 5, Alg. 5) lives in
 ``pecc_oracle_lp.c``; the network is the project's own definition:
 
@@ -38,7 +42,9 @@ from dataclasses import dataclass, asdict
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "pecc_oracle.c"), os.path.join(_HERE, "pecc_oracle_lp.c")]
+_SRCS = [os.path.join(_HERE, "pecc_oracle.c"), os.path.join(_HERE, "pecc_oracle_lp.c"),
+         os.path.join(_HERE, "pecc_oracle_sed.c")]
+_HDRS = [os.path.join(_HERE, "pecc_oracle_types.h")]
 _LIB = os.path.join(_HERE, "_pecc_oracle.so")
 
 STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED",
@@ -58,7 +64,7 @@ def build(force: bool = True) -> str:
 
 def _stale() -> bool:
     return not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
-                                           for f in _SRCS)
+                                           for f in _SRCS + _HDRS)
 
 
 _lib = None
@@ -93,6 +99,22 @@ def lib():
         L.oracle_adjust_container.restype = C.c_int
         L.oracle_adjust_container.argtypes = [C.c_int, dp, dp, C.c_void_p, C.c_double, C.c_int,
                                               C.c_void_p]
+        u64 = C.c_uint64
+        L.oracle_philox4x64.restype = None
+        L.oracle_philox4x64.argtypes = [C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)]
+        L.oracle_sed_shift.restype = None
+        L.oracle_sed_shift.argtypes = [C.c_int, u64, C.c_int32, C.c_int32, C.c_int32, fp]
+        L.oracle_sed_perturb.restype = None
+        L.oracle_sed_perturb.argtypes = [C.c_int, fp, u64, C.c_int32, C.c_int32, C.c_int32, fp]
+        L.oracle_sed_uniform.restype = C.c_double
+        L.oracle_sed_uniform.argtypes = [u64, C.c_int32, C.c_int32]
+        L.oracle_sed_J.restype = C.c_int
+        L.oracle_sed_J.argtypes = [C.c_double, C.c_int]
+        L.oracle_sed_select.restype = C.c_int
+        L.oracle_sed_select.argtypes = [C.c_int, dp, C.c_double, C.c_double, C.c_int]
+        L.oracle_sed.restype = C.c_int
+        L.oracle_sed.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, C.c_int, C.c_int, C.c_double,
+                                 u64, C.c_int32, C.c_void_p]
         i64 = C.c_int64
         L.oracle_bf16_round.restype = None
         L.oracle_bf16_round.argtypes = [i64, fp, fp]
@@ -306,6 +328,65 @@ def adjust_container(xy, R: float, params: DescentParams | None = None, lambda0:
         raise RuntimeError(f"oracle_adjust_container failed ({rc})")
     return x, Rv.value, {"rounds": cr.rounds, "iters": cr.iters, "evals": cr.evals,
                          "last_status": STATUS[cr.last_status], "R": cr.R, "E": cr.E}
+
+
+# ---------------------------------------------------------------------------
+# SED (Sec. 5, Alg. 5) and its random numbers (pecc_oracle_sed.c)
+# ---------------------------------------------------------------------------
+def philox(counter, key):
+    """Philox4x64-10 block at counter (4 words) and key (2 words)."""
+    c = (C.c_uint64 * 4)(*[int(v) & (2 ** 64 - 1) for v in counter])
+    k = (C.c_uint64 * 2)(*[int(v) & (2 ** 64 - 1) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib().oracle_philox4x64(c, k, o)
+    return [int(v) for v in o]
+
+
+def sed_shift(n: int, seed: int, chain: int, it: int, cand: int):
+    r = np.zeros(2 * n, dtype=np.float32)
+    lib().oracle_sed_shift(n, seed, chain, it, cand, r.ctypes.data_as(C.POINTER(C.c_float)))
+    return r.reshape(-1, 2)
+
+
+def sed_perturb(xy32, seed: int, chain: int, it: int, cand: int):
+    xy, px = _f(np.asarray(xy32, dtype=np.float32).reshape(-1, 2))
+    out = np.zeros_like(xy)
+    lib().oracle_sed_perturb(xy.shape[0], px, seed, chain, it, cand,
+                             out.ctypes.data_as(C.POINTER(C.c_float)))
+    return out
+
+
+def sed_uniform(seed: int, chain: int, it: int) -> float:
+    return lib().oracle_sed_uniform(seed, chain, it)
+
+
+def sed_J(E: float, jmax: int = 25) -> int:
+    return lib().oracle_sed_J(float(E), int(jmax))
+
+
+def sed_select(E, E_cur: float, u: float, jmax: int = 25) -> int:
+    E, pE = _d(np.asarray(E).reshape(-1))
+    return lib().oracle_sed_select(E.size, pE, float(E_cur), float(u), int(jmax))
+
+
+class _SedResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("descents", C.c_int32), ("E_best", C.c_double),
+                ("E_start", C.c_double)]
+
+
+def sed(xy, R: float, params: DescentParams | None = None, s_iter: int = 500, m_max: int = 25,
+        e_stop: float = 1e-25, seed: int = 0, chain: int = 0):
+    """Alg. 5 in FP64 from the start xy; returns (best layout, result dict)."""
+    P = params or DescentParams()
+    x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
+    cp = _Params(**asdict(P))
+    cr = _SedResult()
+    rc = lib().oracle_sed(x.shape[0], px, float(R), C.byref(cp), int(s_iter), int(m_max),
+                          float(e_stop), int(seed), int(chain), C.byref(cr))
+    if rc != 0:
+        raise RuntimeError(f"oracle_sed failed ({rc})")
+    return x, {"iterations": cr.iterations, "descents": cr.descents, "E_best": cr.E_best,
+               "E_start": cr.E_start}
 
 
 # ---------------------------------------------------------------------------

@@ -27,6 +27,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include "pecc_oracle_types.h"
+
 /* ------------------------------------------------------------------------ */
 /* Energy and gradient: Def. 3.1 and Def. 3.2, written out pair by pair.     */
 /*                                                                           */
@@ -222,28 +224,6 @@ void oracle_two_loop(int dim, int k, const double *S, const double *Y,
 /* ------------------------------------------------------------------------ */
 /* Descent parameters and outcome (the oracle's own definitions).            */
 /* ------------------------------------------------------------------------ */
-typedef struct {
-    int32_t m;            /* history pairs kept                               */
-    int32_t max_iter;     /* accepted iterations at most                      */
-    int32_t max_halvings; /* step halvings per line search at most            */
-    int32_t ftol_window;  /* iterations spanned by the relative-decrease test */
-    double c1;            /* sufficient-decrease constant                     */
-    double eps_curv;      /* keep (s,y) only if s^T y > eps_curv * y^T y      */
-    double e_feasible;    /* E below this is feasible                         */
-    double g_tol;         /* ||g||_2 at or below this is stationary           */
-    double ftol;          /* relative decrease over the window (0 = off)      */
-    double rad;           /* circle radius used by the energy                 */
-} oracle_params;
-
-typedef struct {
-    int32_t status;
-    int32_t iters;
-    int32_t evals;
-    int32_t resets;
-    double E;
-    double gnorm;
-} oracle_result;
-
 enum { OR_RUNNING = 0, OR_FEASIBLE = 1, OR_STATIONARY = 2, OR_CONVERGED = 3,
        OR_STALLED = 4, OR_MAX_ITER = 5, OR_NONFINITE = 6 };
 
