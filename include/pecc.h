@@ -234,6 +234,45 @@ int pecc_adjust_container(const pecc_instances *inst, float *xy, const pecc_desc
                           void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ========================================================================
+ * SED, the solution-space exploring and descent heuristic (Sec. 5, Alg. 5),
+ * batched over B independent chains (a chain = an instance of `chains`, all
+ * at a fixed radius).  One SED iteration of every chain:
+ *   pecc_sed_plan      m_b = max(1, J(E_cur[b])) candidates, J = ceil(-log10 E)
+ *                      capped at M (E <= 0 counts as the cap), and m_b = 0 once
+ *                      E_best[b] <= e_stop (1e-25); lays the candidates out as
+ *                      one packed batch of B*M instances (slot b*M + j holds n_b
+ *                      circles when j < m_b, none otherwise): cand_offset
+ *                      [B*M + 1], cand_R / cand_R64 [B*M] (the chain's radius);
+ *   pecc_sed_perturb   candidate j of chain b = xy_b + r, every coordinate k
+ *                      shifted by r = u * 1.6 - 0.8 (FP32, two roundings),
+ *                      u = (w >> 40) 2^-24 with w word k mod 4 of the
+ *                      Philox4x64-10 block at counter (k / 4, j, iter, b) and
+ *                      key (seed, 0) (Salmon et al., SC 2011);
+ *   (pecc_lbfgs_descend and pecc_verify on the candidate batch; cand_E [B*M]
+ *    = its energy64)
+ *   pecc_sed_select    Eq. 18: the lowest-energy candidate if it is below
+ *                      E_cur[b] (lowest j among equal energies), else candidate
+ *                      k with probability exp(J_k) / sum exp(J), drawn with
+ *                      u = (w >> 11) 2^-53, w word 0 of the Philox block at
+ *                      counter (2^63, 0, iter, b); xy_cur/E_cur take it, and
+ *                      xy_best/E_best when it is below E_best.  chosen [B]
+ *                      (nullable) gets k, -1 for an inactive chain.
+ * M in [1, PECC_SED_MAX_CAND], B * M <= 2^24.  All arrays are device memory.
+ * ======================================================================== */
+#define PECC_SED_MAX_CAND 64
+
+int pecc_sed_plan(const pecc_instances *chains, const double *E_cur, const double *E_best,
+                  int32_t M, double e_stop, int32_t *m, int32_t *cand_offset, float *cand_R,
+                  double *cand_R64, hipStream_t stream);
+int pecc_sed_perturb(const pecc_instances *chains, const float *xy, int32_t M, const int32_t *m,
+                     const int32_t *cand_offset, uint64_t seed, int32_t iter, float *cand_xy,
+                     hipStream_t stream);
+int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
+                    const int32_t *cand_offset, const float *cand_xy, const double *cand_E,
+                    uint64_t seed, int32_t iter, float *xy_cur, double *E_cur, float *xy_best,
+                    double *E_best, int32_t *chosen, hipStream_t stream);
+
+/* ========================================================================
  * Learned proposal for the perturbation step of SED (Sec. 5, Alg. 5).
  *
  * SED perturbs the current layout and descends again.  Here the

@@ -83,6 +83,12 @@ _sig = {
     "pecc_adjust_container_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_adjust_container": (C.c_int, [_P(pecc_instances), _V, _P(pecc_descent_params), C.c_float,
                                         C.c_int32, _V, _V, _V, C.c_size_t, _V]),
+    "pecc_sed_plan": (C.c_int, [_P(pecc_instances), _V, _V, C.c_int32, C.c_double, _V, _V, _V, _V,
+                                _V]),
+    "pecc_sed_perturb": (C.c_int, [_P(pecc_instances), _V, C.c_int32, _V, _V, C.c_uint64, C.c_int32,
+                                   _V, _V]),
+    "pecc_sed_select": (C.c_int, [_P(pecc_instances), C.c_int32, _V, _V, _V, _V, C.c_uint64,
+                                  C.c_int32, _V, _V, _V, _V, _V, _V]),
     "pecc_features": (C.c_int, [_P(pecc_instances), _V, C.c_int32, _V, _V, _V, _V]),
     "pecc_mlp_forward": (C.c_int, [_V, _V, C.c_int64, _V, _V]),
     "pecc_mlp_grad_workspace_size": (C.c_int, [C.c_int64, _P(C.c_size_t)]),
@@ -316,6 +322,28 @@ def adjust_container(inst: DeviceInstances, xy: torch.Tensor, params: DescentPar
     R_out = torch.empty(inst.B, dtype=torch.float32, device=xy.device)
     pecc_adjust_container(inst, xy, P, lambda0, rounds, R_out, out, ws)
     return R_out, out
+
+
+PECC_SED_MAX_CAND = 64
+
+
+def pecc_sed_plan(chains, E_cur, E_best, M, e_stop, m, cand_offset, cand_R, cand_R64, stream=None):
+    _check(_lib.pecc_sed_plan(C.byref(chains.c()), _ptr(E_cur), _ptr(E_best), int(M), float(e_stop),
+                              _ptr(m), _ptr(cand_offset), _ptr(cand_R), _ptr(cand_R64),
+                              _stream(stream)))
+
+
+def pecc_sed_perturb(chains, xy, M, m, cand_offset, seed, it, cand_xy, stream=None):
+    _check(_lib.pecc_sed_perturb(C.byref(chains.c()), _ptr(xy), int(M), _ptr(m), _ptr(cand_offset),
+                                 int(seed) & (2 ** 64 - 1), int(it), _ptr(cand_xy), _stream(stream)))
+
+
+def pecc_sed_select(chains, M, m, cand_offset, cand_xy, cand_E, seed, it, xy_cur, E_cur, xy_best,
+                    E_best, chosen, stream=None):
+    _check(_lib.pecc_sed_select(C.byref(chains.c()), int(M), _ptr(m), _ptr(cand_offset),
+                                _ptr(cand_xy), _ptr(cand_E), int(seed) & (2 ** 64 - 1), int(it),
+                                _ptr(xy_cur), _ptr(E_cur), _ptr(xy_best), _ptr(E_best),
+                                _ptr(chosen), _stream(stream)))
 
 
 def results(out: torch.Tensor) -> np.ndarray:

@@ -427,6 +427,68 @@ int pecc_accept(const pecc_instances *inst, float *xy_cur, double *e_cur, const 
                      fn);
 }
 
+// ---------------------------------------------------------------------------
+// SED (Alg. 5)
+// ---------------------------------------------------------------------------
+static int sed_checks(const char *fn, const pecc_instances *chains, int32_t M)
+{
+    int rc = check_inst(chains, fn);
+    if (rc) return rc;
+    if (M < 1 || M > PECC_SED_MAX_CAND)
+        return fail(PECC_ERR_INVALID, "%s: M = %d outside [1, %d]", fn, M, PECC_SED_MAX_CAND);
+    if ((int64_t)chains->num_instances * M > (1 << 24))
+        return fail(PECC_ERR_INVALID, "%s: chains x M above 2^24", fn);
+    return PECC_OK;
+}
+
+int pecc_sed_plan(const pecc_instances *chains, const double *E_cur, const double *E_best,
+                  int32_t M, double e_stop, int32_t *m, int32_t *cand_offset, float *cand_R,
+                  double *cand_R64, hipStream_t stream)
+{
+    const char *fn = "pecc_sed_plan";
+    int rc = sed_checks(fn, chains, M);
+    if (rc) return rc;
+    if (!E_cur || !E_best || !m || !cand_offset || !cand_R || !cand_R64)
+        return fail(PECC_ERR_INVALID, "%s: every array must be set", fn);
+    return check_hip(pecc::launch_sed_plan(chains->offset, chains->R, chains->R64,
+                                           chains->num_instances, M, E_cur, E_best, e_stop, m,
+                                           cand_offset, cand_R, cand_R64, stream),
+                     fn);
+}
+
+int pecc_sed_perturb(const pecc_instances *chains, const float *xy, int32_t M, const int32_t *m,
+                     const int32_t *cand_offset, uint64_t seed, int32_t iter, float *cand_xy,
+                     hipStream_t stream)
+{
+    const char *fn = "pecc_sed_perturb";
+    int rc = sed_checks(fn, chains, M);
+    if (rc) return rc;
+    if (iter < 0) return fail(PECC_ERR_INVALID, "%s: iter < 0", fn);
+    if (!m || !cand_offset || !cand_xy || (chains->total_n > 0 && !xy))
+        return fail(PECC_ERR_INVALID, "%s: every array must be set", fn);
+    return check_hip(pecc::launch_sed_perturb(chains->offset, xy, chains->num_instances, M, m,
+                                              cand_offset, seed, iter, cand_xy, stream),
+                     fn);
+}
+
+int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
+                    const int32_t *cand_offset, const float *cand_xy, const double *cand_E,
+                    uint64_t seed, int32_t iter, float *xy_cur, double *E_cur, float *xy_best,
+                    double *E_best, int32_t *chosen, hipStream_t stream)
+{
+    const char *fn = "pecc_sed_select";
+    int rc = sed_checks(fn, chains, M);
+    if (rc) return rc;
+    if (iter < 0) return fail(PECC_ERR_INVALID, "%s: iter < 0", fn);
+    if (!m || !cand_offset || !cand_E || !E_cur || !E_best ||
+        (chains->total_n > 0 && (!cand_xy || !xy_cur || !xy_best)))
+        return fail(PECC_ERR_INVALID, "%s: every array must be set", fn);
+    return check_hip(pecc::launch_sed_select(chains->offset, chains->num_instances, M, m,
+                                             cand_offset, cand_xy, cand_E, seed, iter, xy_cur,
+                                             E_cur, xy_best, E_best, chosen, stream),
+                     fn);
+}
+
 }  // extern "C"
 
 static_assert(sizeof(pecc_descent_result) == 40, "result layout");

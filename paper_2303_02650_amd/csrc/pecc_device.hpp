@@ -57,13 +57,16 @@ __device__ __forceinline__ int cell_of(float2 p, const Grid &g)
     return cell_coord(p.y, g) * g.nc + cell_coord(p.x, g);
 }
 
-// FP64 neighbor predicate on FP32 coordinates, each operation rounded once
-// (no fused multiply-add): dx*dx + dy*dy < c2.
+// FP64 neighbor predicate on FP32 coordinates, each operation rounded once:
+// dx*dx + dy*dy < c2.  The operators are written here, under contract(off):
+// operations inlined from helpers keep the contraction permission of the
+// scope they were written in.
 __device__ __forceinline__ bool near64(float2 a, float2 b, double c2)
 {
-    const double dx = __dsub_rn((double)a.x, (double)b.x);
-    const double dy = __dsub_rn((double)a.y, (double)b.y);
-    return __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)) < c2;
+#pragma clang fp contract(off)   // each operation rounded on its own, like the oracle
+    const double dx = (double)a.x - (double)b.x;
+    const double dy = (double)a.y - (double)b.y;
+    return dx * dx + dy * dy < c2;
 }
 
 // ---------------------------------------------------------------------------

@@ -68,4 +68,18 @@ hipError_t launch_propose(const int32_t *offset, const float *xy, int B, int C,
 hipError_t launch_accept(const int32_t *offset, float *xy_cur, double *e_cur, const float *xy_new,
                          const double *e_new, int B, int32_t *accepted, hipStream_t s);
 
+// SED (Alg. 5) over chains: plan, perturbation, selection.
+hipError_t launch_sed_plan(const int32_t *offset, const float *R, const double *R64, int B, int M,
+                           const double *E_cur, const double *E_best, double e_stop,
+                           int32_t *m_out, int32_t *cand_offset, float *cand_R, double *cand_R64,
+                           hipStream_t s);
+hipError_t launch_sed_perturb(const int32_t *offset, const float *xy, int B, int M,
+                              const int32_t *m, const int32_t *cand_offset, uint64_t seed,
+                              int iter, float *cand_xy, hipStream_t s);
+hipError_t launch_sed_select(const int32_t *offset, int B, int M, const int32_t *m,
+                             const int32_t *cand_offset, const float *cand_xy,
+                             const double *cand_E, uint64_t seed, int iter, float *xy_cur,
+                             double *E_cur, float *xy_best, double *E_best, int32_t *chosen,
+                             hipStream_t s);
+
 }  // namespace pecc

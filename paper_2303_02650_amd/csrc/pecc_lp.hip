@@ -68,23 +68,25 @@ struct FeatShared {
 __device__ void feature_quad(const FeatShared &S, const Grid &g, double R, int skip, float2 p,
                              float *f)
 {
+#pragma clang fp contract(off)   // distances rounded operation by operation, like the oracle
     const double px = (double)p.x, py = (double)p.y;
     double e = 0.0;
     int near = 0, dens = 0;
     for_each_candidate(skip, p, g, S.cell_start, S.cell_circ, [&](int j) {
-        const double dx = __dsub_rn(px, (double)S.pos[j].x);
-        const double dy = __dsub_rn(py, (double)S.pos[j].y);
-        const double l2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+#pragma clang fp contract(off)
+        const double dx = px - (double)S.pos[j].x;
+        const double dy = py - (double)S.pos[j].y;
+        const double l2 = dx * dx + dy * dy;
         if (l2 < 4.0) {
-            const double d = __dsub_rn(2.0, sqrt(l2));
-            e = __dadd_rn(e, __dmul_rn(d, d));
+            const double d = 2.0 - sqrt(l2);
+            e = e + d * d;
         }
         near += l2 < 5.29;
         dens += l2 < 16.0;
     });
-    const double rho = sqrt(__dadd_rn(__dmul_rn(px, px), __dmul_rn(py, py)));
-    const double d0 = __dsub_rn(__dadd_rn(rho, 1.0), R);
-    if (d0 > 0.0) e = __dadd_rn(e, __dmul_rn(d0, d0));
+    const double rho = sqrt(px * px + py * py);
+    const double d0 = (rho + 1.0) - R;
+    if (d0 > 0.0) e = e + d0 * d0;
     f[0] = (float)(log10(e + 1e-20) / 20.0 + 1.0);
     f[1] = (float)near;
     f[2] = (float)((R - 1.0 - rho) / R);
