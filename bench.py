@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-gbo", action="store_true", help="skip the geometric batch workload")
     ap.add_argument("--no-lp", action="store_true", help="skip the learned-proposal workload")
     ap.add_argument("--no-adjust", action="store_true", help="skip the container adjustment")
+    ap.add_argument("--no-sed", action="store_true", help="skip the SED chains")
+    ap.add_argument("--sed-iters", type=int, default=10, help="SED iterations of the chains")
     ap.add_argument("--lp-restarts", type=int, default=20000, help="restarts of training data")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
@@ -521,6 +523,33 @@ def main():
         print(f"[bench] lp: train {t_train:.1f} s, stages {tms}, vs random {cmp}", file=sys.stderr,
               flush=True)
         del F, Y
+
+    # ---- SED (Alg. 5): 128 chains, n=1000, R=34.4 ---------------------------
+    if not a.no_sed:
+        from paper_2303_02650_amd.sed import SedChains
+        c5 = synth.C5(128)
+        d5 = P.DeviceInstances.from_host(c5.offset, c5.R)
+        x5 = torch.from_numpy(c5.xy.reshape(-1)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch = SedChains(d5, x5, descent_params(P, a.max_iter), M=25, seed=17)
+        info = ch.run(a.sed_iters)
+        e_start = ch.E_start.cpu().numpy()
+        e_best = ch.E_best.cpu().numpy()
+        line["sed"] = {
+            "workload": f"128 chains, n=1000, R=34.4 (seed 5), {a.sed_iters} SED iterations, "
+                        "J-controlled candidates (M=25), x+r perturbation r in U(-0.8,0.8), "
+                        "Eq. 18 selection",
+            "seconds": time.perf_counter() - t0, "iterations": info["iterations"],
+            "descents": info["descents"],
+            "descents_per_s": info["descents"] / (time.perf_counter() - t0),
+            "feasible_after_first_descent": float((e_start <= 1e-25).mean()),
+            "feasible_after_sed": float((e_best <= 1e-25).mean()),
+            "E_best_median": float(np.median(e_best)), "E_start_median": float(np.median(e_start))}
+        ff = ch.first_feasible.cpu().numpy()
+        line["sed"]["mean_descents_to_first_feasible"] = float(ff[ff > 0].mean()) if (ff > 0).any() else None
+        print(f"[bench] sed: {line['sed']}", file=sys.stderr, flush=True)
+        del ch
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:

@@ -51,6 +51,10 @@ class SedChains:
         self.chosen = torch.zeros(inst.B, dtype=torch.int32, device=dev)
         self.iterations = 0
         self.descents = inst.B
+        # bookkeeping: descents per chain so far, and at its first layout
+        # with E <= e_stop (-1: not yet)
+        self.desc_chain = torch.ones(inst.B, dtype=torch.int64, device=dev)
+        self.first_feasible = torch.where(self.E_best <= e_stop, 1, -1).to(torch.int64)
 
     def step(self) -> int:
         """One SED iteration of every active chain; returns the number of
@@ -70,6 +74,9 @@ class SedChains:
                         self.seed, it, self.xy, self.E_cur, self.xy_best, self.E_best, self.chosen)
         self.iterations += 1
         self.descents += active
+        self.desc_chain += self.m.to(torch.int64)
+        newly = (self.E_best <= self.e_stop) & (self.first_feasible < 0)
+        self.first_feasible = torch.where(newly, self.desc_chain, self.first_feasible)
         return active
 
     def run(self, s_iter: int) -> dict:
