@@ -22,6 +22,11 @@ The solution-space exploring and descent heuristic (Sec. 5, Alg. 5) lives in
 ``pecc_oracle_sed.c``: philox (Philox4x64-10), sed_shift / sed_perturb,
 sed_uniform, sed_J, sed_select, sed.
 
+The k-batch partitions of Sec. 4.1, the batch descent of Alg. 1 with the
+batches visited in order and the adaptive neighbor maintenance of Alg. 3
+live in ``pecc_oracle_part.c``: partition (sector, annulus, fence, random),
+gamma_energy (E over a neighbor structure built elsewhere), gbo_seq_descend.
+
 The learned proposal of the perturbation step (Sec. 5, Alg. 5) lives in
 ``pecc_oracle_lp.c``; the network is the project's own definition:
 
@@ -43,7 +48,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "pecc_oracle.c"), os.path.join(_HERE, "pecc_oracle_lp.c"),
-         os.path.join(_HERE, "pecc_oracle_sed.c")]
+         os.path.join(_HERE, "pecc_oracle_sed.c"), os.path.join(_HERE, "pecc_oracle_part.c")]
 _HDRS = [os.path.join(_HERE, "pecc_oracle_types.h")]
 _LIB = os.path.join(_HERE, "_pecc_oracle.so")
 
@@ -117,6 +122,13 @@ def lib():
                                  u64, C.c_int32, C.c_void_p]
         i64 = C.c_int64
         L.oracle_bf16_round.restype = None
+        L.oracle_partition.argtypes = [C.c_int, fp, C.c_int, C.c_int, u64, C.c_int32, ip]
+        L.oracle_partition.restype = C.c_int
+        L.oracle_gamma_energy.argtypes = [C.c_int, dp, dp, C.c_double, C.c_double]
+        L.oracle_gamma_energy.restype = C.c_double
+        L.oracle_gbo_seq_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, ip, C.c_int,
+                                             C.c_void_p, C.c_void_p, dp]
+        L.oracle_gbo_seq_descend.restype = C.c_int
         L.oracle_bf16_round.argtypes = [i64, fp, fp]
         L.oracle_features.restype = C.c_int
         L.oracle_features.argtypes = [C.c_int, fp, C.c_double, C.c_int, ip, fp, dp]
@@ -473,3 +485,67 @@ def propose(xy32, cand_circle, cand_dest, scores, k: int):
                                sel.ctypes.data_as(C.POINTER(C.c_int32)),
                                out.ctypes.data_as(C.POINTER(C.c_float)))
     return sel[:cnt], out
+
+
+# ---------------------------------------------------------------------------
+# Partitions (Sec. 4.1), sequential batch descent (Alg. 1), ANM (Alg. 3)
+# ---------------------------------------------------------------------------
+PARTITIONS = {"sector": 0, "annulus": 1, "fence": 2, "random": 3}
+
+
+def partition(xy32, kind: str, k: int, seed: int = 0, instance: int = 0):
+    """batch_of (int32 [n]) of the k-batch partition `kind` of FP32 positions."""
+    x, px = _f(np.asarray(xy32).reshape(-1, 2))
+    out = np.zeros(x.shape[0], dtype=np.int32)
+    rc = lib().oracle_partition(x.shape[0], px, PARTITIONS[kind], int(k), int(seed) & (2 ** 64 - 1),
+                                int(instance), out.ctypes.data_as(C.POINTER(C.c_int32)))
+    if rc != 0:
+        raise ValueError(f"oracle_partition failed ({rc})")
+    return out
+
+
+def gamma_energy(ref, xy, R: float, lcut: float = 4.0) -> float:
+    """E of xy over the neighbor structure built at ref with l_cut."""
+    r, pr = _d(np.asarray(ref).reshape(-1, 2))
+    x, px = _d(np.asarray(xy).reshape(-1, 2))
+    return lib().oracle_gamma_energy(r.shape[0], pr, px, float(R), float(lcut))
+
+
+class _SeqParams(C.Structure):
+    _fields_ = [("max_outer", C.c_int32), ("anm", C.c_int32), ("lcut", C.c_double)]
+
+
+class _SeqResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("visits", C.c_int32),
+                ("evals", C.c_int32), ("stalled_visits", C.c_int32), ("anm_checks", C.c_int32),
+                ("anm_changes", C.c_int32), ("pad", C.c_int32), ("E", C.c_double),
+                ("gsum", C.c_double)]
+
+
+def gbo_seq_descend(xy, R: float, batch_of, k: int, params: DescentParams | None = None,
+                    max_outer: int = 5000, anm: bool = False, lcut: float = 4.0,
+                    trace: bool = False):
+    """Alg. 1 with the given partition, batches visited in order, FP64.
+    Returns (xy_final, result, trace)."""
+    P = params or DescentParams()
+    x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
+    bo = np.ascontiguousarray(np.asarray(batch_of), dtype=np.int32)
+    if bo.size != x.shape[0]:
+        raise ValueError("batch_of needs one entry per circle")
+    cp = _Params(**asdict(P))
+    sp = _SeqParams(int(max_outer), 1 if anm else 0, float(lcut))
+    cr = _SeqResult()
+    tr = np.zeros(max_outer + 1, dtype=np.float64) if trace else None
+    rc = lib().oracle_gbo_seq_descend(x.shape[0], px, float(R), C.byref(cp),
+                                      bo.ctypes.data_as(C.POINTER(C.c_int32)), int(k),
+                                      C.byref(sp), C.byref(cr),
+                                      tr.ctypes.data_as(C.POINTER(C.c_double)) if trace else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle_gbo_seq_descend failed ({rc})")
+    res = {"status": STATUS[cr.status], "outer": cr.outer, "visits": cr.visits,
+           "evals": cr.evals, "stalled_visits": cr.stalled_visits,
+           "anm_checks": cr.anm_checks, "anm_changes": cr.anm_changes, "E": cr.E,
+           "gsum": cr.gsum}
+    if trace:
+        tr = tr[:cr.outer + 1]
+    return x, res, tr
