@@ -45,6 +45,85 @@ DESCENT_TRAFFIC_BYTES_256 = 4.7e6
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
 
+def kbatch_study(P, a, dev, stream):
+    """Alg. 1 with k equal batches of the sector, annulus, fence and random
+    partitions, batches visited in order, on random starts of n = 1000 at
+    R = 34.4: descents per second, outer iterations and the converged FP64
+    energy for every (partition, k), and the ratio of the best k's time to
+    k = 1's (the quantities of the paper's partition and batch-number
+    study).  One launch per setting covers every start; with more starts
+    than compute units the rate reflects the mean descent time."""
+    import torch
+    import synth
+    c4 = synth.C4(a.kbatch_instances)
+    d = P.DeviceInstances.from_host(c4.offset, c4.R)
+    x0 = torch.from_numpy(c4.xy.reshape(-1)).to(dev)
+    x = torch.empty_like(x0)
+    ws = torch.empty(P.pecc_gbo_kbatch_descend_workspace_size(d), dtype=torch.uint8, device=dev)
+    out = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    e64 = torch.empty(d.B, dtype=torch.float64, device=dev)
+    feas = torch.empty(d.B, dtype=torch.int32, device=dev)
+    bo = torch.empty(d.total_n, dtype=torch.int32, device=dev)
+    ks = [int(v) for v in a.kbatch_ks.split(",") if v]
+
+    def one(kind, k, anm=False):
+        prm = descent_params(P, a.max_iter)
+        if anm:
+            prm.cutoff = 4.0
+        pc = prm.c()
+        P.pecc_partition(d, x0, P.PARTITIONS[kind], k, 17, bo)
+        x.copy_(x0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.pecc_gbo_kbatch_descend(d, x, bo, k, 1 if anm else 0, pc, out, ws)
+        e1.record(stream)
+        P.pecc_verify(d, x, 1e-20, e64, None, None, feas)
+        torch.cuda.synchronize()
+        r = P.results(out)
+        ms = e0.elapsed_time(e1)
+        return {"kernel_ms": ms, "descents_per_s": d.B / (ms / 1e3),
+                "outer_iters_mean": float(r["iters"].mean()),
+                "evals_mean": float(r["evals"].mean()),
+                "rebuilds_mean": float(r["rebuilds"].mean()),
+                "E64_mean": float(e64.cpu().numpy().mean()),
+                "feasible_fraction": float(feas.cpu().numpy().mean()),
+                "status_counts": {P.STATUS[s]: int((r["status"] == s).sum()) for s in np.unique(r["status"])}}
+
+    one("sector", 5)                                  # warm-up
+    table = {}
+    for kind in P.PARTITIONS:
+        for k in ks:
+            if kind != "sector" and k == 1:
+                continue                              # k = 1 is one batch for every kind
+            table[f"{kind}_k{k}"] = one(kind, k)
+            print(f"[bench] kbatch {kind} k={k}: {table[f'{kind}_k{k}']['kernel_ms']:.1f} ms, "
+                  f"E64 mean {table[f'{kind}_k{k}']['E64_mean']:.3g}", file=sys.stderr, flush=True)
+    table["sector_k5_anm_lcut4"] = one("sector", 5, anm=True)
+    if 1 in ks:
+        table["sector_k1_anm_lcut4"] = one("sector", 1, anm=True)
+    summary = {}
+    if 1 in ks:
+        t1 = table["sector_k1"]["kernel_ms"]
+        for kind in P.PARTITIONS:
+            cand = {k: table[f"{kind}_k{k}"]["kernel_ms"] for k in ks if k > 1 and f"{kind}_k{k}" in table}
+            if cand:
+                kb = min(cand, key=cand.get)
+                summary[kind] = {"best_k": kb, "best_ms": cand[kb], "ratio_to_k1": cand[kb] / t1}
+    whole = descent_params(P, a.max_iter).c()
+    x.copy_(x0)
+    wws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    P.pecc_lbfgs_descend(d, x, whole, out, wws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return {"workload": f"{d.B} random starts, n=1000, R=34.4 (seed 3); k equal batches of each "
+                        f"partition visited in order, one L-BFGS iteration per visit; cutoff 2.3 "
+                        f"with skin 0.15, or ANM with l_cut 4",
+            "settings": table, "best_k_by_partition": summary,
+            "whole_instance_descent_ms": e0.elapsed_time(e1)}
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +142,10 @@ def parse():
     ap.add_argument("--no-lp", action="store_true", help="skip the learned-proposal workload")
     ap.add_argument("--no-adjust", action="store_true", help="skip the container adjustment")
     ap.add_argument("--no-sed", action="store_true", help="skip the SED chains")
+    ap.add_argument("--no-kbatch", action="store_true", help="skip the k-batch partition study")
+    ap.add_argument("--kbatch-ks", default="1,2,3,5,7,10,15", help="batch counts of the study")
+    ap.add_argument("--kbatch-instances", type=int, default=512,
+                    help="random starts per setting (more than the CUs: the rate reflects the mean)")
     ap.add_argument("--sed-iters", type=int, default=10, help="SED iterations of the chains")
     ap.add_argument("--lp-restarts", type=int, default=20000, help="restarts of training data")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
@@ -442,6 +525,10 @@ def main():
         line["gbo"] = {"workload": f"64 random starts, n=1000, R=34.4, {gblocks} x {gblocks} blocks "
                                    f"(~{1000 // (gblocks * gblocks)} circles per batch)",
                        **gbo}
+
+    # ---- k-batch descent (Alg. 1) over the four partitions of Sec. 4.1 -----
+    if not a.no_kbatch:
+        line["kbatch"] = kbatch_study(P, a, dev, stream)
 
     # ---- learned proposal: 128 x n=1000, R=34.4, 4096 candidates ----------
     if not a.no_lp:

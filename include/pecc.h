@@ -199,6 +199,73 @@ int pecc_gbo_descend(const pecc_instances *inst, float *xy,
                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * k-batch partitions (Sec. 4.1).  The circles of every instance are ordered
+ * by a key and cut into k consecutive runs: batch p holds floor(n/k) +
+ * [p < n mod k] circles (every size floor(n/k) or ceil(n/k), the larger
+ * ones first).  Equal keys order by circle index.  Keys:
+ *   PECC_PARTITION_SECTOR   polar angle atan2(y, x) in (-pi, pi] (the full
+ *                           angle: arctan(y/x) would merge opposite
+ *                           quadrants), compared exactly from the FP32
+ *                           positions without evaluating an angle;
+ *   PECC_PARTITION_ANNULUS  x^2 + y^2 (FP64);
+ *   PECC_PARTITION_FENCE    x;
+ *   PECC_PARTITION_RANDOM   word 0 of Philox4x64-10 at counter (i, b, 0,
+ *                           2^62) with key (seed, 0), i the circle's index
+ *                           in instance b: a uniformly random partition.
+ * xy: device [2*total_n]; batch_of: device int32 [total_n] (caller-owned),
+ * batch of every circle.  seed is used by the random kind only.
+ * Errors: PECC_ERR_INVALID for an unknown kind, k outside [1, PECC_MAX_N]
+ * or null pointers.  Instances with invalid offsets are skipped.
+ * ------------------------------------------------------------------------ */
+#define PECC_PARTITION_SECTOR  0
+#define PECC_PARTITION_ANNULUS 1
+#define PECC_PARTITION_FENCE   2
+#define PECC_PARTITION_RANDOM  3
+int pecc_partition(const pecc_instances *inst, const float *xy, int32_t kind, int32_t k,
+                   uint64_t seed, int32_t *batch_of, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * k-batch descent: Alg. 1 over a given partition, the batches visited one
+ * after another (Gauss-Seidel), each visit one L-BFGS iteration (the
+ * limited-memory reading of Eq. 8-11, memory params->m per batch) on the
+ * batch energy of Eq. 7 with the other circles where the earlier visits
+ * left them.  Every outer iteration starts with the whole instance's
+ * energy and the stop tests: FP64 energy of unit circles < e_feasible
+ * (FEASIBLE), the sum over batches of ||g(x_p)||_2 of the previous outer
+ * iteration <= g_tol (STATIONARY, the stop rule of Alg. 1), relative
+ * decrease of E over ftol_window outer iterations <= ftol (CONVERGED), every
+ * visit of the previous outer iteration failed its line search (STALLED),
+ * max_iter outer iterations (MAX_ITER).  The line searches test FP64 batch
+ * energies once E32 < tau64 at the top of an outer iteration.
+ * anm = 0: neighbor lists with cutoff params->cutoff, rebuilt when a circle
+ * moved more than skin_half (every pair within the cutoff is seen).
+ * anm = 1: ANM (Sec. 4.3, Alg. 3) with l_cut = params->cutoff (the paper:
+ * 4): after every outer iteration a counter grows, and once it reaches the
+ * deferring length the lists of the current positions are compared with
+ * the stored ones -- different: they replace them and the length is reset
+ * to 1; equal: the length doubles.  Energies are then over the stored lists
+ * only (a pair that came closer than 2 without being listed is not seen;
+ * a circle with more than 32 neighbors within l_cut makes the sweep use the
+ * cell grid of the last rebuild, a superset).
+ * batch_of: device int32 [total_n], batch of every circle in [0, k) (e.g.
+ * from pecc_partition); an id outside makes that instance report
+ * PECC_STATUS_BAD_INSTANCE.  With one non-empty batch the descent is the
+ * whole-instance L-BFGS descent (ANM after every iteration).
+ * Results: iters = outer iterations, gnorm = the sum of batch gradient
+ * norms of the last outer iteration, E32 = whole-instance FP32 energy,
+ * E64 = FP64 energy of unit circles (over the lists).  rebuilds counts list
+ * builds.  Workspace: pecc_gbo_kbatch_descend_workspace_size bytes.
+ * Errors: PECC_ERR_INVALID for k outside [1, PECC_MAX_BATCHES], anm not 0
+ * or 1, or the descent parameters pecc_lbfgs_descend rejects.
+ * ------------------------------------------------------------------------ */
+#define PECC_MAX_BATCHES 16
+int pecc_gbo_kbatch_descend_workspace_size(const pecc_instances *inst, size_t *bytes /*host*/);
+int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t *batch_of,
+                            int32_t k, int32_t anm, const pecc_descent_params *params /*host*/,
+                            pecc_descent_result *out /*device [B]*/, void *workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * FP64 feasibility check of Eq. 1-2 through the energy of Def. 3.2 with
  * unit circles: every pair i<j of each instance is enumerated (no list),
  * in FP64 on the FP32 positions.  Per instance: energy64 = E,

@@ -80,6 +80,10 @@ _sig = {
     "pecc_gbo_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                    C.c_void_p]),
+    "pecc_partition": (C.c_int, [_P(pecc_instances), _V, C.c_int32, C.c_int32, C.c_uint64, _V, _V]),
+    "pecc_gbo_kbatch_descend_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
+    "pecc_gbo_kbatch_descend": (C.c_int, [_P(pecc_instances), _V, _V, C.c_int32, C.c_int32,
+                                          _P(pecc_descent_params), _V, _V, C.c_size_t, _V]),
     "pecc_adjust_container_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_adjust_container": (C.c_int, [_P(pecc_instances), _V, _P(pecc_descent_params), C.c_float,
                                         C.c_int32, _V, _V, _V, C.c_size_t, _V]),
@@ -295,6 +299,53 @@ def gbo_descend(inst: DeviceInstances, xy: torch.Tensor, params: DescentParams |
         workspace = torch.empty(pecc_gbo_descend_workspace_size(inst, blocks), dtype=torch.uint8,
                                 device=xy.device)
     pecc_gbo_descend(inst, xy, P, blocks, sweep_fp64, out, workspace)
+    return out
+
+
+PARTITIONS = {"sector": 0, "annulus": 1, "fence": 2, "random": 3}
+PECC_MAX_BATCHES = 16
+
+
+def pecc_partition(inst, xy, kind: int, k: int, seed: int, batch_of, stream=None):
+    _check(_lib.pecc_partition(C.byref(inst.c()), _ptr(xy), int(kind), int(k),
+                               int(seed) & (2 ** 64 - 1), _ptr(batch_of), _stream(stream)))
+
+
+def partition(inst: DeviceInstances, xy: torch.Tensor, kind: str = "sector", k: int = 5,
+              seed: int = 0) -> torch.Tensor:
+    """k-batch partition of every instance (Sec. 4.1): int32 batch ids."""
+    out = torch.empty(inst.total_n, dtype=torch.int32, device=xy.device)
+    pecc_partition(inst, xy, PARTITIONS[kind], k, seed, out)
+    return out
+
+
+def pecc_gbo_kbatch_descend_workspace_size(inst: DeviceInstances) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_gbo_kbatch_descend_workspace_size(C.byref(inst.c()), C.byref(b)))
+    return b.value
+
+
+def pecc_gbo_kbatch_descend(inst, xy, batch_of, k: int, anm: int, params: pecc_descent_params,
+                            out, workspace, stream=None):
+    _check(_lib.pecc_gbo_kbatch_descend(C.byref(inst.c()), _ptr(xy), _ptr(batch_of), int(k),
+                                        int(anm), C.byref(params), _ptr(out), _ptr(workspace),
+                                        workspace.numel() * workspace.element_size(),
+                                        _stream(stream)))
+
+
+def gbo_kbatch_descend(inst: DeviceInstances, xy: torch.Tensor, batch_of: torch.Tensor, k: int,
+                       params: DescentParams | None = None, anm: bool = False,
+                       workspace: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """Alg. 1 over the partition batch_of (k batches, visited in order) of
+    every instance, in place; anm selects the neighbor maintenance of Alg. 3
+    (l_cut = params.cutoff).  Returns the device result buffer."""
+    P = (params or DescentParams()).c()
+    if out is None:
+        out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=xy.device)
+    if workspace is None:
+        workspace = torch.empty(pecc_gbo_kbatch_descend_workspace_size(inst), dtype=torch.uint8,
+                                device=xy.device)
+    pecc_gbo_kbatch_descend(inst, xy, batch_of, k, 1 if anm else 0, P, out, workspace)
     return out
 
 

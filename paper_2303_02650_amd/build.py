@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpecc.so")
-SOURCES = ["pecc_api.hip", "pecc_kernels.hip", "pecc_descent.hip", "pecc_gbo.hip", "pecc_lp.hip", "pecc_sed.hip"]
+SOURCES = ["pecc_api.hip", "pecc_kernels.hip", "pecc_descent.hip", "pecc_gbo.hip", "pecc_lp.hip", "pecc_sed.hip",
+           "pecc_part.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

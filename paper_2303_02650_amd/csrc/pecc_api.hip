@@ -174,6 +174,8 @@ int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs
     a->tau64 = p->tau64;
     a->lambda0 = 0.f;
     a->rounds = 0;
+    a->nbat = 1;
+    a->anm = 0;
     return PECC_OK;
 }
 
@@ -232,6 +234,57 @@ int pecc_adjust_container(const pecc_instances *inst, float *xy, const pecc_desc
     return check_hip(pecc::launch_adjust(inst->offset, inst->R, xy, inst->num_instances,
                                          inst->total_n, a, R_out, out, (int32_t *)workspace, grid,
                                          stream),
+                     fn);
+}
+
+int pecc_partition(const pecc_instances *inst, const float *xy, int32_t kind, int32_t k,
+                   uint64_t seed, int32_t *batch_of, hipStream_t stream)
+{
+    const char *fn = "pecc_partition";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (kind < PECC_PARTITION_SECTOR || kind > PECC_PARTITION_RANDOM)
+        return fail(PECC_ERR_INVALID, "%s: unknown kind %d", fn, kind);
+    if (k < 1 || k > PECC_MAX_N) return fail(PECC_ERR_INVALID, "%s: k = %d outside [1, %d]", fn, k, PECC_MAX_N);
+    if (inst->total_n > 0 && (!xy || !batch_of))
+        return fail(PECC_ERR_INVALID, "%s: xy and batch_of must be set", fn);
+    return check_hip(pecc::launch_partition(inst->offset, xy, inst->num_instances, inst->total_n,
+                                            kind, k, seed, batch_of, stream),
+                     fn);
+}
+
+int pecc_gbo_kbatch_descend_workspace_size(const pecc_instances *inst, size_t *bytes)
+{
+    return pecc_lbfgs_descend_workspace_size(inst, bytes);
+}
+
+int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t *batch_of,
+                            int32_t k, int32_t anm, const pecc_descent_params *p,
+                            pecc_descent_result *out, void *workspace, size_t workspace_bytes,
+                            hipStream_t stream)
+{
+    const char *fn = "pecc_gbo_kbatch_descend";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && (!xy || !batch_of))
+        return fail(PECC_ERR_INVALID, "%s: xy and batch_of must be set", fn);
+    if (k < 1 || k > PECC_MAX_BATCHES)
+        return fail(PECC_ERR_INVALID, "%s: k = %d outside [1, %d]", fn, k, PECC_MAX_BATCHES);
+    if (anm != 0 && anm != 1) return fail(PECC_ERR_INVALID, "%s: anm must be 0 or 1", fn);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
+    a.nbat = k;
+    a.anm = anm;
+    size_t need = 0;
+    pecc_lbfgs_descend_workspace_size(inst, &need);
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    const int grid = pecc::descend_grid(inst->num_instances);
+    return check_hip(pecc::launch_seq(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
+                                      inst->total_n, a, batch_of, out, (int32_t *)workspace, grid,
+                                      stream),
                      fn);
 }
 
@@ -493,4 +546,5 @@ int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
 
 static_assert(sizeof(pecc_descent_result) == 40, "result layout");
 static_assert(sizeof(pecc_descent_params) == 64, "params layout");
+static_assert(PECC_MAX_BATCHES == pecc::kMaxSeqBatches, "batch limit");
 static_assert(sizeof(pecc_adam_params) == 16, "adam params layout");

@@ -17,10 +17,17 @@
 //     the energy), so a trial costs two workgroup barriers.
 // Workgroups take instances from a queue, largest n first, until the queue
 // is empty (the launch is sized to the resident capacity of the device).
+//
+// Three instantiations share this code: the whole-instance descent, the
+// container adjustment (the radius as a variable) and the batch descent of
+// Alg. 1 over a given k-batch partition, visited one batch after another
+// (see the kernel's comment).
 #include "pecc_device.hpp"
 #include "pecc_host.hpp"
 #include "pecc_launch.hpp"
 #include "pecc_lbfgs.hpp"
+
+#include <type_traits>
 
 namespace pecc {
 
@@ -28,13 +35,17 @@ constexpr int kDB = 512;                  // threads per workgroup
 constexpr int kDW = kDB / kWave;          // waves per workgroup
 constexpr int kCPT = kMaxN / kDB;         // circles per thread
 constexpr int kEll = 24;                  // neighbor slots per circle (ELL list)
+constexpr int kEllSeq = 32;               // ... in the batch descent (l_cut up to 4)
 
+enum : int { kModeWhole = 0, kModeAdj = 1, kModeSeq = 2 };
+
+template <int ELL>
 struct DescentShared {
     float2 pos[kMaxN];
     int cell_start[kMaxCells + 1];
     uint16_t cell_circ[kMaxN];
     uint16_t slot_tmp[kMaxN];
-    uint16_t list[kEll][kMaxN];    // slot-major: lanes read consecutive entries
+    uint16_t list[ELL][kMaxN];     // slot-major: lanes read consecutive entries
     uint8_t  list_n[kMaxN];
     float red[2][kDW][kWave];
     double red64[2][kDW][2];
@@ -43,12 +54,23 @@ struct DescentShared {
     uint16_t bsrc[2][kNB * kNB];   // Gram update sources, see gram_source
     int scan_tmp[kDW + 1];
     int flag[2];
-    int over;                      // a circle had more than kEll neighbors
+    int over;                      // a circle had more than ELL neighbors
     int work;
 };
 
+// Batch descent only: the saved Gram matrix of every batch, batch ids and
+// batch sizes.
+struct SeqShared {
+    float BmP[kMaxSeqBatches][kNB * kNB];
+    uint8_t bat[kMaxN];
+    int cnt[kMaxSeqBatches];
+};
+struct NoShared {
+    int unused;
+};
+
 // Evaluation requests of the descent's state machine.
-enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2 };
+enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2, kReqTotal = 3 };
 
 // ADJ: container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins
 // the variables, the objective is U = E + lambda R^2 and A.rounds
@@ -58,14 +80,39 @@ enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2 };
 // product added, and the unit-circle energy slot carries sum_i d_i0 instead,
 // from which dU/dR = -2 sum_i d_i0 + 2 lambda R.  FP32 throughout (no FP64
 // regime, no FEASIBLE stop: U > 0); Rout[b] receives the final radius.
-template <bool ADJ>
+//
+// SEQ: batch descent of Alg. 1 over the partition part[] into A.nbat
+// batches.  An outer iteration visits the non-empty batches in index order;
+// a visit is one L-BFGS iteration on the batch energy of Eq. 7 with the
+// other circles where the earlier visits left them: an evaluation at the
+// current positions (the batch's gradient and its Gram row), the two-loop
+// over the batch's own history (each circle's history registers belong to
+// its batch; the batch's Gram matrix is saved in LDS between visits), and
+// the backtracking line search, whose accepted trial gives the curvature
+// pair.  Only the batch's circles are swept and move; a pair counts in the
+// batch energy when its other circle is outside the batch or has the
+// higher index (each pair once).  A visit whose line search fails leaves
+// the batch where it was.  Every outer iteration starts with an evaluation
+// of the whole instance (E, and the FP64 energies for the FEASIBLE test)
+// and the stop tests on it; the sum of the visits' gradient norms stands
+// for ||g||.  A.anm = 1 replaces the displacement trigger of the neighbor
+// lists by ANM (Alg. 3): after every outer iteration cnt += 1, and once cnt
+// >= len the lists of the current positions are compared with the stored
+// ones -- different: rebuild, len = 1; equal: len doubles.  With one
+// non-empty batch the descent is the whole-instance one (ANM after every
+// iteration, the point re-evaluated when the lists change).
+template <int MODE>
 __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ Rv,
     const double *__restrict__ Rv64, float *__restrict__ xy,
     int B, int64_t total_n, DescentArgs A, DescentResultDev *__restrict__ out,
-    int32_t *__restrict__ queue, float *__restrict__ Rout)
+    int32_t *__restrict__ queue, float *__restrict__ Rout, const int32_t *__restrict__ part)
 {
-    __shared__ DescentShared sh;
+    constexpr bool ADJ = MODE == kModeAdj;
+    constexpr bool SEQ = MODE == kModeSeq;
+    constexpr int ELL = SEQ ? kEllSeq : kEll;
+    __shared__ DescentShared<ELL> sh;
+    __shared__ std::conditional_t<SEQ, SeqShared, NoShared> sq;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
@@ -102,6 +149,49 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         const double R64 = Rv64 ? Rv64[b] : (double)R;
         const Grid grid = make_grid(R, A.h_req);
 
+        // ---- batch descent: batch of every circle, batch sizes --------------
+        int batc[kCPT] = {};            // batch of each circle of this thread
+        bool visits = false;            // more than one non-empty batch
+        int first_b = 0;                // first non-empty batch
+        if constexpr (SEQ) {
+            for (int q = tid; q < kMaxSeqBatches; q += kDB) sq.cnt[q] = 0;
+            for (int q = tid; q < kMaxSeqBatches * kNB * kNB; q += kDB)
+                sq.BmP[q / (kNB * kNB)][q % (kNB * kNB)] = 0.f;
+            __syncthreads();
+            int bad = 0;
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) {
+                const int i = tid + c * kDB;
+                if (i < n) {
+                    const int v = part[off + i];
+                    if (v < 0 || v >= A.nbat) {
+                        bad = 1;
+                    } else {
+                        batc[c] = v;
+                        sq.bat[i] = (uint8_t)v;
+                        atomicAdd(&sq.cnt[v], 1);
+                    }
+                }
+            }
+            if (__syncthreads_or(bad)) {
+                if (tid == 0) {
+                    DescentResultDev r = {};
+                    r.status = 7;  // BAD_INSTANCE: a batch id out of range
+                    r.E32 = __builtin_nanf("");
+                    r.gnorm = __builtin_nanf("");
+                    r.E64 = -1.0;
+                    out[b] = r;
+                }
+                continue;
+            }
+            int ne = 0;
+            first_b = -1;
+            for (int q = 0; q < A.nbat; ++q)
+                if (sq.cnt[q] > 0) { ++ne; if (first_b < 0) first_b = q; }
+            if (first_b < 0) first_b = 0;
+            visits = ne > 1;
+        }
+
         // ---- per-thread state (circle c of this thread is tid + c*kDB) ----
         bool act[kCPT];
         float2 x[kCPT], g[kCPT], xr[kCPT], p[kCPT];
@@ -130,8 +220,83 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         float E = 0.0f, gp = 0.f, alpha = 0.f;
         double ehist = 0.0;               // lane w: energy of iteration w mod (W+1)
         int status = 0, it = 0, h = 0;
-        int req = kReqInit;
+        int req = (SEQ && visits) ? kReqTotal : kReqInit;
         const int W = A.ftol_window;
+        // batch descent (uniform): current batch, history count of batch p
+        // at lane p, gradient-norm sums, visits and stalled visits of the
+        // outer iteration, ANM counter and deferring length
+        int cb = first_b, kb_v = 0;
+        float gsum = 0.f, gsum_prev = 0.f, E_tot = 0.f;
+        int nvis = 0, nstall = 0;
+        int anm_cnt = 0, anm_len = 1, anm_it = 0;
+
+        // relative decrease of the accepted energy over the last W iterations
+        // (lane w of ehist holds iteration w mod (W + 1)) at most ftol
+        auto decreased_too_little = [&](double Eacc) -> bool {
+            const int src = (it - W) % (W + 1);
+            const long long bits = __builtin_bit_cast(long long, ehist);
+            const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
+            const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+            const double eold = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+            return eold - Eacc <= (double)A.ftol * eold;
+        };
+        // batch descent: batch bb's saved Gram matrix into B (every wave
+        // writes the same values and reads back its own)
+        auto load_gram = [&](int bb) {
+            if constexpr (SEQ) {
+                const int ln = (int)threadIdx.x & (kWave - 1);
+#pragma unroll
+                for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
+                    const int ent = ln + kWave * r;
+                    if (ent < kNB * kNB) sh.Bm[cur][ent] = sq.BmP[bb][ent];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        };
+        // ANM (Alg. 3), one call: cnt += 1; once cnt >= len the neighbor
+        // lists of the current positions are compared with the stored ones
+        // (same predicate; as sets).  Different (or the stored lists did not
+        // fit): the next evaluation rebuilds them and len = 1; equal: len
+        // doubles.  Returns whether the lists change.
+        auto anm_step = [&]() -> bool {
+            if (++anm_cnt < anm_len) return false;
+            anm_cnt = 0;
+            const int t0 = (int)threadIdx.x;
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c)
+                if (act[c]) sh.pos[t0 + c * kDB] = x[c];
+            __syncthreads();
+            bin_circles<kDB>(sh.pos, n, grid, sh.cell_start, sh.cell_circ, sh.slot_tmp,
+                             sh.scan_tmp);
+            int diff = overflow ? 1 : 0;
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) {
+                const int i = t0 + c * kDB;
+                if (act[c] && !diff) {
+                    const int old = sh.list_n[i];
+                    int m = 0;
+                    for_each_candidate(i, x[c], grid, sh.cell_start, sh.cell_circ, [&](int j) {
+                        if (near_cut(x[c], sh.pos[j], c2lo, c2hi, A.c2)) {
+                            bool found = false;
+                            for (int t = 0; t < old; ++t) found = found || sh.list[t][i] == j;
+                            if (!found) diff = 1;
+                            ++m;
+                        }
+                    });
+                    if (m != old) diff = 1;
+                }
+            }
+            const bool changed = __syncthreads_or(diff) != 0;
+            if (changed) {
+                if (t0 == 0) sh.flag[tcount & 1] = 1;
+                anm_len = 1;
+            } else if (anm_len < (1 << 29)) {
+                anm_len *= 2;
+            }
+            return changed;
+        };
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
         if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; }
@@ -164,6 +329,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // ================= one evaluation ==================================
             float2 xt[kCPT], sc[kCPT];
             const int par = tcount & 1;
+            // batch descent: only the current batch is swept (masked); the
+            // evaluation at the top of an outer iteration covers every
+            // circle and always takes the FP64 energies
+            const bool masked = SEQ && visits && req != kReqTotal;
+            const bool want64 = fp64 || (SEQ && req == kReqTotal);
+            bool inb[kCPT];
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) inb[c] = !masked || batc[c] == cb;
             // container radius of this evaluation (a variable only when adjusting)
             const float Rt = ADJ ? (req == kReqTrial ? fmaf(alpha, pR, Rz) : Rz) : R;
 #pragma unroll
@@ -175,7 +348,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     sh.pos[tid + c * kDB] = xt[c];
                     const double dx = (double)xt[c].x - (double)xr[c].x;
                     const double dy = (double)xt[c].y - (double)xr[c].y;
-                    if (dx * dx + dy * dy > A.skin2) sh.flag[par] = 1;
+                    if (!(SEQ && A.anm) && dx * dx + dy * dy > A.skin2) sh.flag[par] = 1;
                 }
             }
             __syncthreads();                                            // B1
@@ -199,7 +372,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 }
                 __syncthreads();
                 // one pass: every circle writes its neighbors into its own
-                // kEll slots; more than kEll switches this list epoch to
+                // ELL slots; more than ELL switches this list epoch to
                 // sweeping the cell grid instead
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
@@ -215,14 +388,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             for (int t = a; t < z; ++t) {
                                 const int j = sh.cell_circ[t];
                                 if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) {
-                                    if (m < kEll) sh.list[m][i] = (uint16_t)j;
+                                    if (m < ELL) sh.list[m][i] = (uint16_t)j;
                                     ++m;
                                     up += j > i;
                                 }
                             }
                         }
-                        if (m > kEll) sh.over = 1;
-                        sh.list_n[i] = (uint8_t)(m < kEll ? m : kEll);
+                        if (m > ELL) sh.over = 1;
+                        sh.list_n[i] = (uint8_t)(m < ELL ? m : ELL);
                         half_mine[c] = up;
                         xr[c] = xt[c];
                     }
@@ -234,7 +407,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             ++tcount;
             ++evals;
 #pragma unroll
-            for (int c = 0; c < kCPT; ++c) pair_mine += half_mine[c];
+            for (int c = 0; c < kCPT; ++c) pair_mine += inb[c] ? half_mine[c] : 0;
             // ---- pair sweep: energy and gradient of this thread's circles ----
             // Both circles of the thread walk their lists in one loop, so their
             // list and position reads overlap; each circle still adds its
@@ -254,7 +427,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 int mm = 0;
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
-                    mc[c] = act[c] ? sh.list_n[tid + c * kDB] : 0;
+                    mc[c] = (act[c] && inb[c]) ? sh.list_n[tid + c * kDB] : 0;
                     mm = mc[c] > mm ? mc[c] : mm;
                 }
                 for (int t = 0; t < mm; ++t) {
@@ -273,10 +446,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         if (t < mc[c]) {
                             const int j = jv[c];
                             const float2 q = xt[c];
-                            pair_term32(q, pj[c], j > i, two_r, four_r2, ecA[c], e1cA[c], gxA[c], gyA[c]);
+                            // each pair once: from its lower index, or (batch
+                            // energy, Eq. 7) from the batch's end
+                            bool hf = j > i;
+                            if constexpr (SEQ) if (masked) hf = hf || sq.bat[j] != cb;
+                            pair_term32(q, pj[c], hf, two_r, four_r2, ecA[c], e1cA[c], gxA[c], gyA[c]);
                             // FP64 energies only where FP32 sees (nearly) an overlap:
                             // outside a 1e-5 band the FP64 terms are zero
-                            if (fp64 && j > i) {
+                            if (want64 && hf) {
                                 const float dx = q.x - pj[c].x, dy = q.y - pj[c].y;
                                 if (dx * dx + dy * dy < four_r2_band)
                                     pair_term64(q, pj[c], two_r64, four_r2_64, eocA[c], etcA[c]);
@@ -290,7 +467,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const int i = tid + c * kDB;
                 const float2 q = xt[c];
                 float gx = gxA[c], gy = gyA[c];
-                if (act[c]) {
+                if (act[c] && inb[c]) {
                     float ec = ecA[c], e1c = e1cA[c];
                     double eoc = eocA[c], etc = etcA[c];
                     if (overflow) {
@@ -305,8 +482,10 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                 const int j = sh.cell_circ[t];
                                 if (j == i) continue;
                                 const float2 pj = sh.pos[j];
-                                pair_term32(q, pj, j > i, two_r, four_r2, ec, e1c, gx, gy);
-                                if (fp64 && j > i) {
+                                bool hf = j > i;
+                                if constexpr (SEQ) if (masked) hf = hf || sq.bat[j] != cb;
+                                pair_term32(q, pj, hf, two_r, four_r2, ec, e1c, gx, gy);
+                                if (want64 && hf) {
                                     const float dx = q.x - pj.x, dy = q.y - pj.y;
                                     if (dx * dx + dy * dy < four_r2_band)
                                         pair_term64(q, pj, two_r64, four_r2_64, eoc, etc);
@@ -332,7 +511,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     const float kc = 2.f * d0 * ir;
                     gx += kc * q.x;
                     gy += kc * q.y;
-                    if (fp64) {
+                    if (want64) {
                         const double r64 = sqrt((double)q.x * q.x + (double)q.y * q.y);
                         const double c0 = r64 + rad64 - R64;
                         if (c0 > 0.0) eo += c0 * c0;
@@ -346,12 +525,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                 }
                 gt[c] = make_float2(gx, gy);
-                yc[c] = make_float2(gx - g[c].x, gy - g[c].y);
+                yc[c] = inb[c] ? make_float2(gx - g[c].x, gy - g[c].y) : make_float2(0.f, 0.f);
             }
             // ---- fused reduction: 63 dot products and E in one pass ----------
             const float wsum = wave_reduce_scatter(gt, sc, yc, S, Y, e, e1);
             sh.red[par][wv][lane_slot(lane)] = wsum;
-            if (fp64) {
+            if (want64) {
                 const double wo = wave_sum(eo), wt = wave_sum(et);
                 if (lane == 0) { sh.red64[par][wv][0] = wo; sh.red64[par][wv][1] = wt; }
             }
@@ -360,7 +539,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
             for (int w = 0; w < kDW; ++w) tot += sh.red[par][w][lane];
             double so = 0.0, st = 0.0;
-            if (fp64) {
+            if (want64) {
 #pragma unroll
                 for (int w = 0; w < kDW; ++w) { so += sh.red64[par][w][0]; st += sh.red64[par][w][1]; }
             }
@@ -397,7 +576,35 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             const float E1t = lane_value(tot, sE1);
 
             // ================= what the evaluation was for =====================
+            if constexpr (SEQ) {
+                if (visits && req == kReqTotal) {
+                    // ---- top of an outer iteration: stop tests on the whole instance
+                    E_tot = Et;
+                    E64o = so;
+                    E64t = st;
+                    const double Eacc = fp64 ? E64o : (double)E_tot;
+                    if (!isfinite(E_tot)) { status = 6; break; }
+                    if (E64t < A.e_feasible) { status = 1; break; }
+                    if (it > 0 && gsum_prev <= A.g_tol) { status = 2; break; }
+                    if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) { status = 3; break; }
+                    if (lane == it % (W + 1)) ehist = Eacc;
+                    if (it > 0 && nvis > 0 && nstall == nvis) { status = 4; break; }
+                    if (it >= A.max_iter) { status = 5; break; }
+                    if (!fp64 && A.tau64 > 0.0 && (double)fminf(E_tot, E1t) < A.tau64) fp64 = true;
+                    gsum = 0.f;
+                    nvis = 0;
+                    nstall = 0;
+                    cb = first_b;
+                    // the batch's saved Gram matrix; no wave reads B before
+                    // the next evaluation's barriers
+                    load_gram(cb);
+                    k = __builtin_amdgcn_readlane(kb_v, cb);
+                    req = kReqInit;
+                    continue;
+                }
+            }
             bool accept = false, push = false;
+            bool vend = false;     // batch descent: the visit ends with this evaluation
             if (req == kReqTrial) {
                 const bool ok = fp64 ? so <= E64o + (double)A.c1 * (double)alpha * (double)gp
                                      : Et <= E + A.c1 * alpha * gp;
@@ -405,10 +612,16 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     accept = true;
                     const float sy = lane_value(tot, sScYc), yy = lane_value(tot, sYcYc);
                     push = sy > A.eps_curv * yy;
+                    vend = SEQ && visits;
                 } else {
                     alpha *= 0.5f;
-                    if (++h > A.max_halvings) { status = 4; break; }   // STALLED
-                    continue;
+                    if (++h > A.max_halvings) {
+                        if (!(SEQ && visits)) { status = 4; break; }   // STALLED
+                        vend = true;                                   // the batch stays
+                        ++nstall;
+                    } else {
+                        continue;
+                    }
                 }
             } else if (req == kReqInit) {
                 accept = true;   // g and the g row of B from this evaluation
@@ -439,7 +652,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
-                    if (push) {
+                    if (push && inb[c]) {
 #pragma unroll
                         for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
                         S[kMM - 1][c] = sc[c];
@@ -462,36 +675,71 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     Rz = Rt;
                     gR = gRt;
                 }
-                if (req == kReqTrial) ++it;
+                if (req == kReqTrial && !(SEQ && visits)) ++it;   // visits: outer iterations
                 E = Et;
                 if (fp64) { E64o = so; E64t = st; }
                 // FP64 regime once either FP32 energy is small: with a contact
                 // margin the unit circles can be overlap-free while E (radius
                 // rad) still sums (2 mu)^2 over every contact
-                if (!ADJ && !fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
+                if (!ADJ && !(SEQ && visits) && !fp64 && A.tau64 > 0.0 &&
+                    (double)fminf(E, E1t) < A.tau64) {
                     fp64 = true;
                     req = kReqFp64;          // FP64 energies of x before going on
                     continue;
                 }
             }
 
+            if constexpr (SEQ) {
+                if (visits && vend) {
+                    // ---- end of a visit: save the batch's Gram matrix (every
+                    // wave has finished with B), then the next batch
+                    kb_v = lane == cb ? k : kb_v;
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
+                        const int ent = lane + kWave * r;
+                        if (ent < kNB * kNB) sq.BmP[cb][ent] = sh.Bm[cur][ent];
+                    }
+                    __syncthreads();
+                    int nx = cb + 1;
+                    while (nx < A.nbat && sq.cnt[nx] == 0) ++nx;
+                    if (nx >= A.nbat) {           // outer iteration done
+                        ++it;
+                        gsum_prev = gsum;
+                        if (A.anm) anm_step();
+                        req = kReqTotal;
+                        continue;
+                    }
+                    cb = nx;
+                    load_gram(cb);
+                    k = __builtin_amdgcn_readlane(kb_v, cb);
+                    req = kReqInit;
+                    continue;
+                }
+                if (!visits && A.anm && it > anm_it) {
+                    // one batch: ANM after every iteration; changed lists
+                    // re-evaluate the current point over the new lists
+                    anm_it = it;
+                    if (anm_step()) { req = kReqInit; continue; }
+                }
+            }
+
             // ================= top of an iteration: stop tests =================
             const float gg = sh.Bm[cur][kG * kNB + kG];
             const float gn = sqrtf(fmaxf(gg, 0.f));
-            const double Eacc = fp64 ? E64o : (double)E;
-            if (!isfinite(E) || !isfinite(gn)) { status = 6; break; }
-            if (fp64 && E64t < A.e_feasible) { status = 1; break; }
-            if (gn <= A.g_tol) { status = 2; break; }
-            if (A.ftol > 0.f && it >= W) {
-                const int src = (it - W) % (W + 1);
-                const long long bits = __builtin_bit_cast(long long, ehist);
-                const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
-                const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
-                const double eold = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-                if (eold - Eacc <= (double)A.ftol * eold) { status = 3; break; }
+            if (SEQ && visits) {
+                // a visit's first evaluation: its gradient norm joins the sum
+                gsum += gn;
+                ++nvis;
+            } else {
+                const double Eacc = fp64 ? E64o : (double)E;
+                if (!isfinite(E) || !isfinite(gn)) { status = 6; break; }
+                if (fp64 && E64t < A.e_feasible) { status = 1; break; }
+                if (gn <= A.g_tol) { status = 2; break; }
+                if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) { status = 3; break; }
+                if (lane == it % (W + 1)) ehist = Eacc;
+                if (it >= A.max_iter) { status = 5; break; }
             }
-            if (lane == it % (W + 1)) ehist = Eacc;
-            if (it >= A.max_iter) { status = 5; break; }
 
             // ================= direction: two-loop recursion on B ===============
             // Lane l holds row l of B (the basis s_0..s_9, y_0..y_9, g), so
@@ -547,7 +795,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         px -= csj * S[j][c].x + cyj * Y[j][c].x;
                         py -= csj * S[j][c].y + cyj * Y[j][c].y;
                     }
-                    p[c] = make_float2(px, py);
+                    p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(px, py)
+                                                              : make_float2(0.f, 0.f);
                 }
                 if constexpr (ADJ) {
                     float pr = -gam * gR;
@@ -561,7 +810,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (k > 0 && !(gp < 0.f)) {
                 k = 0;
 #pragma unroll
-                for (int c = 0; c < kCPT; ++c) p[c] = make_float2(-g[c].x, -g[c].y);
+                for (int c = 0; c < kCPT; ++c)
+                    p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(-g[c].x, -g[c].y)
+                                                              : make_float2(0.f, 0.f);
                 if constexpr (ADJ) pR = -gR;
                 gp = -gg;
             }
@@ -604,6 +855,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             r.E32 = (ADJ && A.rounds > 0) ? E - 2.f * lam * Rz * Rz : E;
             r.gnorm = sqrtf(fmaxf(sh.Bm[cur][kG * kNB + kG], 0.f));
             r.E64 = fp64 ? E64t : -1.0;
+            if (SEQ && visits) {
+                // outer iterations; whole-instance energies; the sum of the
+                // batch gradient norms of the last outer iteration
+                r.E32 = E_tot;
+                r.gnorm = gsum_prev;
+                r.E64 = E64t;
+            }
             out[b] = r;
             if constexpr (ADJ) Rout[b] = Rz;
         }
@@ -643,7 +901,7 @@ __global__ __launch_bounds__(kQB) void queue_init_kernel(const int32_t *__restri
 int descend_grid(int B)
 {
     static std::atomic<int> per_cu[kMaxDevices];
-    const int cap = current_device_cus() * resident_per_cu(lbfgs_descend_kernel<false>, kDB, per_cu);
+    const int cap = current_device_cus() * resident_per_cu(lbfgs_descend_kernel<kModeWhole>, kDB, per_cu);
     return B < cap ? B : cap;
 }
 
@@ -659,9 +917,9 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
 {
     queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
     if (grid < 1) grid = 1;
-    lbfgs_descend_kernel<false><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
-                                                     reinterpret_cast<DescentResultDev *>(out),
-                                                     queue, nullptr);
+    lbfgs_descend_kernel<kModeWhole><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
+                                                          reinterpret_cast<DescentResultDev *>(out),
+                                                          queue, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -671,9 +929,21 @@ hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B
 {
     queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
     if (grid < 1) grid = 1;
-    lbfgs_descend_kernel<true><<<grid, kDB, 0, s>>>(offset, R, nullptr, xy, B, total_n, a,
-                                                    reinterpret_cast<DescentResultDev *>(out),
-                                                    queue, Rout);
+    lbfgs_descend_kernel<kModeAdj><<<grid, kDB, 0, s>>>(offset, R, nullptr, xy, B, total_n, a,
+                                                        reinterpret_cast<DescentResultDev *>(out),
+                                                        queue, Rout, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_seq(const int32_t *offset, const float *R, const double *R64, float *xy, int B,
+                      int64_t total_n, const DescentArgs &a, const int32_t *batch_of, void *out,
+                      int32_t *queue, int grid, hipStream_t s)
+{
+    queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
+    if (grid < 1) grid = 1;
+    lbfgs_descend_kernel<kModeSeq><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
+                                                        reinterpret_cast<DescentResultDev *>(out),
+                                                        queue, nullptr, batch_of);
     return hipGetLastError();
 }
 

@@ -26,7 +26,11 @@ struct DescentArgs {
     double c2, skin2, e_feasible, tau64;
     float lambda0;    // container adjustment: first penalty coefficient
     int rounds;       // container adjustment: minimisations, lambda halved after each
+    int nbat;         // batch descent: batches of the partition (1..kMaxSeqBatches)
+    int anm;          // batch descent: 1 = adaptive neighbor maintenance (Alg. 3)
 };
+
+constexpr int kMaxSeqBatches = 16;   // batches of the batch descent at most
 
 struct DescentResultDev;  // layout-identical to pecc_descent_result
 
@@ -41,6 +45,16 @@ int descend_grid(int B);   // persistent workgroups to launch for B instances
 hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B,
                          int64_t total_n, const DescentArgs &a, float *Rout, void *out,
                          int32_t *queue, int grid, hipStream_t s);
+
+// Batch descent of Alg. 1 over a given partition (batch_of: global circle
+// index -> batch in [0, a.nbat)), batches visited in order.
+hipError_t launch_seq(const int32_t *offset, const float *R, const double *R64, float *xy, int B,
+                      int64_t total_n, const DescentArgs &a, const int32_t *batch_of, void *out,
+                      int32_t *queue, int grid, hipStream_t s);
+
+// k-batch partitions of Sec. 4.1 (kind: 0 sector, 1 annulus, 2 fence, 3 random).
+hipError_t launch_partition(const int32_t *offset, const float *xy, int B, int64_t total_n,
+                            int kind, int k, uint64_t seed, int32_t *batch_of, hipStream_t s);
 
 // Geometric batch descent: workspace bytes and launch.
 size_t gbo_workspace_bytes(int B, int blocks);

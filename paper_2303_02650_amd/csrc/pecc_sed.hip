@@ -13,9 +13,7 @@
 //            current energy, else one drawn with probabilities softmax(J),
 //            the uniform from Philox at counter (2^63, 0, iteration, b);
 //            the chain's best record follows.
-// Philox4x64-10: Salmon, Moraes, Dror & Shaw, SC 2011 (two 64 x 64 -> 128
-// multiplies per round, key bumped by two Weyl constants), written from that
-// definition.
+// Philox4x64-10 (philox4x64 in pecc_device.hpp) gives every random number.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,32 +23,6 @@
 
 namespace pecc {
 namespace {
-
-struct U64x4 {
-    uint64_t w[4];
-};
-
-__device__ __forceinline__ U64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                            uint64_t k0, uint64_t k1)
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
-        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += W0;
-        k1 += W1;
-    }
-    U64x4 o;
-    o.w[0] = c0; o.w[1] = c1; o.w[2] = c2; o.w[3] = c3;
-    return o;
-}
 
 // J = ceil(-log10 E) clipped to jmax; E <= 0 (or NaN) gives jmax.
 __device__ __forceinline__ int sed_J(double E, int jmax)
