@@ -127,7 +127,9 @@ def lib():
         L.oracle_gamma_energy.argtypes = [C.c_int, dp, dp, C.c_double, C.c_double]
         L.oracle_gamma_energy.restype = C.c_double
         L.oracle_gbo_seq_descend.argtypes = [C.c_int, dp, C.c_double, C.c_void_p, ip, C.c_int,
-                                             C.c_void_p, C.c_void_p, dp]
+                                             C.c_void_p, C.c_void_p, dp, dp]
+        L.oracle_bfgs_update.argtypes = [C.c_int, dp, dp, dp]
+        L.oracle_bfgs_update.restype = None
         L.oracle_gbo_seq_descend.restype = C.c_int
         L.oracle_bf16_round.argtypes = [i64, fp, fp]
         L.oracle_features.restype = C.c_int
@@ -512,7 +514,17 @@ def gamma_energy(ref, xy, R: float, lcut: float = 4.0) -> float:
 
 
 class _SeqParams(C.Structure):
-    _fields_ = [("max_outer", C.c_int32), ("anm", C.c_int32), ("lcut", C.c_double)]
+    _fields_ = [("max_outer", C.c_int32), ("anm", C.c_int32), ("lcut", C.c_double),
+                ("dense", C.c_int32), ("pad", C.c_int32)]
+
+
+def bfgs_update(H, u, v):
+    """Eq. 11 applied to a symmetric H (returns a new array)."""
+    H = np.array(H, dtype=np.float64, copy=True, order="C")
+    u, pu = _d(np.asarray(u).reshape(-1))
+    v, pv = _d(np.asarray(v).reshape(-1))
+    lib().oracle_bfgs_update(u.size, H.ctypes.data_as(C.POINTER(C.c_double)), pu, pv)
+    return H
 
 
 class _SeqResult(C.Structure):
@@ -524,22 +536,26 @@ class _SeqResult(C.Structure):
 
 def gbo_seq_descend(xy, R: float, batch_of, k: int, params: DescentParams | None = None,
                     max_outer: int = 5000, anm: bool = False, lcut: float = 4.0,
-                    trace: bool = False):
-    """Alg. 1 with the given partition, batches visited in order, FP64.
-    Returns (xy_final, result, trace)."""
+                    trace: bool = False, dense: bool = False, xtrace: bool = False):
+    """Alg. 1 with the given partition, batches visited in order, FP64
+    (dense: the paper's per-batch inverse-Hessian matrices).  Returns
+    (xy_final, result, trace), and the positions at the top of every outer
+    iteration as a fourth item when xtrace is set."""
     P = params or DescentParams()
     x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
     bo = np.ascontiguousarray(np.asarray(batch_of), dtype=np.int32)
     if bo.size != x.shape[0]:
         raise ValueError("batch_of needs one entry per circle")
     cp = _Params(**asdict(P))
-    sp = _SeqParams(int(max_outer), 1 if anm else 0, float(lcut))
+    sp = _SeqParams(int(max_outer), 1 if anm else 0, float(lcut), 1 if dense else 0, 0)
     cr = _SeqResult()
     tr = np.zeros(max_outer + 1, dtype=np.float64) if trace else None
+    xt = np.zeros((max_outer + 1, x.shape[0], 2), dtype=np.float64) if xtrace else None
     rc = lib().oracle_gbo_seq_descend(x.shape[0], px, float(R), C.byref(cp),
                                       bo.ctypes.data_as(C.POINTER(C.c_int32)), int(k),
                                       C.byref(sp), C.byref(cr),
-                                      tr.ctypes.data_as(C.POINTER(C.c_double)) if trace else None)
+                                      tr.ctypes.data_as(C.POINTER(C.c_double)) if trace else None,
+                                      xt.ctypes.data_as(C.POINTER(C.c_double)) if xtrace else None)
     if rc != 0:
         raise RuntimeError(f"oracle_gbo_seq_descend failed ({rc})")
     res = {"status": STATUS[cr.status], "outer": cr.outer, "visits": cr.visits,
@@ -548,4 +564,6 @@ def gbo_seq_descend(xy, R: float, batch_of, k: int, params: DescentParams | None
            "gsum": cr.gsum}
     if trace:
         tr = tr[:cr.outer + 1]
+    if xtrace:
+        return x, res, tr, xt[:cr.outer + 1]
     return x, res, tr

@@ -292,13 +292,25 @@ double oracle_gamma_energy(int n, const double *ref, const double *xy, double R,
 /*     len = 1, Gamma = Gamma'; otherwise cnt = 0, len = 2 len.  Gamma is   */
 /*     built at the start with cnt = 0, len = 1;                            */
 /*   E of the new layout (over Gamma when ANM is on).                       */
+/* dense = 1 replaces the limited-memory history by the paper's dense        */
+/* inverse-Hessian approximation H_p of every batch (Eq. 8-11): H_p = I at    */
+/* the start, p = -H_p g, and after an accepted step with s'y > eps_curv y'y */
+/* (u = s, v = y, beta = v'u)                                               */
+/*   H_p <- (I - u v'/beta) H_p (I - v u'/beta) + u u'/beta,                */
+/* evaluated as H - (w u' + u w')/beta + (v'w/beta^2 + 1/beta) u u' with     */
+/* w = H v (the same matrix, H symmetric).  A direction that is not a       */
+/* descent direction resets H_p to I; alpha0 = 1 once H_p has been updated, */
+/* 1/max(1,||g||) before.                                                   */
 /* xy (2n) is updated in place; trace (nullable, max_outer + 1) gets E at   */
-/* the top of every outer iteration.                                        */
+/* the top of every outer iteration, xtrace (nullable, (max_outer + 1) 2n)  */
+/* the positions there.                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t max_outer;
     int32_t anm;          /* 0: exact energies over every pair; 1: over Gamma, ANM */
     double lcut;          /* l_cut of Gamma (4 in the paper)                 */
+    int32_t dense;        /* 1: dense H_p per batch (Eq. 11) instead of L-BFGS */
+    int32_t pad;
 } oracle_seq_params;
 
 typedef struct {
@@ -324,9 +336,36 @@ static double dotp(int d, const double *a, const double *b)
     return s;
 }
 
+/* H <- H - (w u' + u w')/beta + (v'w/beta^2 + 1/beta) u u', w = H v: the
+ * product form of Eq. 11 multiplied out for a symmetric H (d x d, row-major). */
+void oracle_bfgs_update(int d, double *H, const double *u, const double *v)
+{
+    double *w = malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
+    if (!w) return;
+    double beta = 0.0, vw = 0.0;
+    for (int r = 0; r < d; ++r) {
+        double acc = 0.0;
+        for (int c = 0; c < d; ++c) acc += H[(size_t)r * d + c] * v[c];
+        w[r] = acc;
+        beta += v[r] * u[r];
+    }
+    for (int r = 0; r < d; ++r) vw += v[r] * w[r];
+    const double a = vw / (beta * beta) + 1.0 / beta;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            H[(size_t)r * d + c] += -(w[r] * u[c] + u[r] * w[c]) / beta + a * u[r] * u[c];
+    free(w);
+}
+
+static void set_identity(int d, double *H)
+{
+    memset(H, 0, sizeof(double) * (size_t)d * d);
+    for (int r = 0; r < d; ++r) H[(size_t)r * d + r] = 1.0;
+}
+
 int oracle_gbo_seq_descend(int n, double *xy, double R, const oracle_params *P,
                            const int32_t *batch_of, int k, const oracle_seq_params *Q,
-                           oracle_seq_result *res, double *trace)
+                           oracle_seq_result *res, double *trace, double *xtrace)
 {
     const int m = P->m;
     if (k < 1 || m < 1 || m > 64) return -2;
@@ -361,8 +400,15 @@ int oracle_gbo_seq_descend(int n, double *xy, double R, const oracle_params *P,
     }
     for (int p = 0; p < k; ++p) {
         const size_t dim = 2 * (size_t)(cnt[p] > 0 ? cnt[p] : 1);
-        Sh[p] = calloc((size_t)m * dim, sizeof(double));
-        Yh[p] = calloc((size_t)m * dim, sizeof(double));
+        if (Q->dense) {
+            /* Sh[p] holds H_p (dim x dim); Yh[p] is unused */
+            Sh[p] = malloc(sizeof(double) * dim * dim);
+            Yh[p] = malloc(sizeof(double));
+            if (Sh[p]) set_identity((int)dim, Sh[p]);
+        } else {
+            Sh[p] = calloc((size_t)m * dim, sizeof(double));
+            Yh[p] = calloc((size_t)m * dim, sizeof(double));
+        }
         if (!Sh[p] || !Yh[p]) { rc = -1; goto done; }
     }
     int anm_cnt = 0, anm_len = 1, checks = 0, changes = 0;
@@ -377,6 +423,7 @@ int oracle_gbo_seq_descend(int n, double *xy, double R, const oracle_params *P,
     double gsum_prev = -1.0;
     for (t = 0;; ++t) {
         if (trace) trace[t] = E;
+        if (xtrace) memcpy(xtrace + (size_t)t * 2 * n, xy, sizeof(double) * 2 * (size_t)n);
         if (!isfinite(E)) { status = SQ_NONFINITE; break; }
         if (E < P->e_feasible) { status = SQ_FEASIBLE; break; }
         if (t > 0 && gsum_prev <= P->g_tol) { status = SQ_STATIONARY; break; }
@@ -408,11 +455,21 @@ int oracle_gbo_seq_descend(int n, double *xy, double R, const oracle_params *P,
             }
             const double gn = sqrt(dotp(dim, bg, bg));
             gsum += gn;
-            oracle_two_loop(dim, kh[p], Sh[p], Yh[p], bg, bp);
-            for (int d = 0; d < dim; ++d) bp[d] = -bp[d];
+            if (Q->dense) {
+                const double *H = Sh[p];
+                for (int r = 0; r < dim; ++r) {
+                    double acc = 0.0;
+                    for (int c = 0; c < dim; ++c) acc += H[(size_t)r * dim + c] * bg[c];
+                    bp[r] = -acc;
+                }
+            } else {
+                oracle_two_loop(dim, kh[p], Sh[p], Yh[p], bg, bp);
+                for (int d = 0; d < dim; ++d) bp[d] = -bp[d];
+            }
             double gp = dotp(dim, bg, bp);
             if (kh[p] > 0 && !(gp < 0.0)) {
                 kh[p] = 0;
+                if (Q->dense) set_identity(dim, Sh[p]);
                 for (int d = 0; d < dim; ++d) bp[d] = -bg[d];
                 gp = dotp(dim, bg, bp);
             }
@@ -440,14 +497,19 @@ int oracle_gbo_seq_descend(int n, double *xy, double R, const oracle_params *P,
                     }
                 }
                 if (sy > P->eps_curv * yy) {
-                    if (kh[p] == m) {
-                        memmove(Sh[p], Sh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
-                        memmove(Yh[p], Yh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
-                        kh[p] = m - 1;
+                    if (Q->dense) {
+                        oracle_bfgs_update(dim, Sh[p], bs, by);
+                        if (kh[p] < m) ++kh[p];
+                    } else {
+                        if (kh[p] == m) {
+                            memmove(Sh[p], Sh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
+                            memmove(Yh[p], Yh[p] + dim, sizeof(double) * (size_t)(m - 1) * dim);
+                            kh[p] = m - 1;
+                        }
+                        memcpy(Sh[p] + (size_t)kh[p] * dim, bs, sizeof(double) * dim);
+                        memcpy(Yh[p] + (size_t)kh[p] * dim, by, sizeof(double) * dim);
+                        ++kh[p];
                     }
-                    memcpy(Sh[p] + (size_t)kh[p] * dim, bs, sizeof(double) * dim);
-                    memcpy(Yh[p] + (size_t)kh[p] * dim, by, sizeof(double) * dim);
-                    ++kh[p];
                 }
             } else {
                 for (int q = 0; q < np; ++q) {

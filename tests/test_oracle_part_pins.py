@@ -201,3 +201,65 @@ def test_gamma_energy_exact_until_a_circle_moves_by_one():
     j = int(np.argmax(np.hypot(ref[:, 0] - ref[i, 0], ref[:, 1] - ref[i, 1])))
     far[i] = ref[j] + np.array([0.5, 0.0])
     assert oracle.gamma_energy(ref, far, R, 4.0) < oracle.energy(far, R) - 1.0
+
+
+# ---------------------------------------------------------------------------
+# The paper's dense inverse-Hessian update (Eq. 10-11) and the dense batch
+# descent that uses it
+# ---------------------------------------------------------------------------
+def eq11(H, u, v):
+    """Eq. 11 as printed: (I - u v'/b) H (I - v u'/b) + u u'/b, b = v'u."""
+    b = float(v @ u)
+    I = np.eye(len(u))
+    return (I - np.outer(u, v) / b) @ H @ (I - np.outer(v, u) / b) + np.outer(u, u) / b
+
+
+@pytest.mark.parametrize("d", [1, 4, 37])
+def test_bfgs_update_is_eq11(d):
+    rng = np.random.default_rng(d)
+    A = rng.normal(size=(d, d))
+    H = A @ A.T + d * np.eye(d)
+    u = rng.normal(size=d)
+    v = u + 0.3 * rng.normal(size=d)
+    if v @ u <= 0:
+        v = -v
+    Hn = oracle.bfgs_update(H, u, v)
+    assert np.allclose(Hn, eq11(H, u, v), rtol=1e-12, atol=1e-12 * np.abs(H).max())
+    assert np.allclose(Hn @ v, u, rtol=1e-10, atol=1e-12)          # secant condition
+    assert np.allclose(Hn, Hn.T, rtol=0, atol=1e-12 * np.abs(Hn).max())
+    assert np.linalg.eigvalsh(Hn).min() > 0                          # stays positive definite
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_dense_steps_follow_eq8_to_eq11(k):
+    """Every visit moves its batch by -alpha H_p g(x_p), alpha a power of two
+    times alpha0, with H_p rebuilt here from the visited steps by the printed
+    Eq. 11 (numpy products) starting from I."""
+    inst = synth.C1()
+    x0, R = inst.instance(0).astype(np.float64), float(inst.R[0])
+    b = oracle.partition(inst.instance(0), "sector", k)
+    T = 12
+    _, res, _, xs = oracle.gbo_seq_descend(x0, R, b, k, oracle.DescentParams(g_tol=0.0),
+                                           max_outer=T, dense=True, xtrace=True)
+    assert res["outer"] == T and res["stalled_visits"] == 0
+    H = {p: np.eye(2 * int((b == p).sum())) for p in range(k)}
+    updated = {p: False for p in range(k)}
+    for t in range(T):
+        cur = xs[t].copy()
+        for p in range(k):
+            m = b == p
+            g = oracle.energy_grad(cur, R)[3][m].reshape(-1)
+            d = -H[p] @ g
+            nxt = cur.copy()
+            nxt[m] = xs[t + 1][m]
+            step = (nxt[m] - cur[m]).reshape(-1)
+            alpha = float(step @ d) / float(d @ d)
+            assert np.abs(step - alpha * d).max() <= 1e-8 * np.abs(step).max(), (t, p)
+            a0 = 1.0 if updated[p] else 1.0 / max(1.0, float(np.linalg.norm(g)))
+            j = np.log2(a0 / alpha)
+            assert abs(j - round(j)) < 1e-6 and round(j) >= 0, (t, p, alpha)
+            y = oracle.energy_grad(nxt, R)[3][m].reshape(-1) - g
+            if step @ y > 1e-8 * (y @ y):
+                H[p] = eq11(H[p], step, y)
+                updated[p] = True
+            cur = nxt
