@@ -109,6 +109,49 @@ def kbatch_study(P, a, dev, stream):
             if cand:
                 kb = min(cand, key=cand.get)
                 summary[kind] = {"best_k": kb, "best_ms": cand[kb], "ratio_to_k1": cand[kb] / t1}
+    # the paper's dense per-batch matrices: sector batches, fewer starts
+    dense = {}
+    if a.kbatch_dense_instances > 0:
+        cd = synth.C4(a.kbatch_dense_instances)
+        dd = P.DeviceInstances.from_host(cd.offset, cd.R)
+        xd0 = torch.from_numpy(cd.xy.reshape(-1)).to(dev)
+        xd = torch.empty_like(xd0)
+        bod = torch.empty(dd.total_n, dtype=torch.int32, device=dev)
+        outd = torch.empty(dd.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        e64d = torch.empty(dd.B, dtype=torch.float64, device=dev)
+        feasd = torch.empty(dd.B, dtype=torch.int32, device=dev)
+        pc = descent_params(P, a.max_iter).c()
+        for k in ks:
+            mb = -(-1000 // k)
+            wsd = torch.empty(P.pecc_gbo_kbatch_bfgs_workspace_size(dd, mb), dtype=torch.uint8,
+                              device=dev)
+            P.pecc_partition(dd, xd0, P.PARTITIONS["sector"], k, 17, bod)
+            xd.copy_(xd0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.pecc_gbo_kbatch_bfgs_descend(dd, xd, bod, k, 0, mb, pc, outd, wsd)
+            e1.record(stream)
+            P.pecc_verify(dd, xd, 1e-20, e64d, None, None, feasd)
+            torch.cuda.synchronize()
+            r = P.results(outd)
+            ms = e0.elapsed_time(e1)
+            dense[f"sector_k{k}"] = {
+                "kernel_ms": ms, "descents_per_s": dd.B / (ms / 1e3),
+                "matrix_bytes_per_instance": 4 * k * (2 * mb) ** 2,
+                "outer_iters_mean": float(r["iters"].mean()), "evals_mean": float(r["evals"].mean()),
+                "E64_mean": float(e64d.cpu().numpy().mean()),
+                "feasible_fraction": float(feasd.cpu().numpy().mean()),
+                "status_counts": {P.STATUS[s]: int((r["status"] == s).sum()) for s in np.unique(r["status"])}}
+            del wsd
+            print(f"[bench] kbatch dense sector k={k}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        if 1 in ks:
+            t1 = dense["sector_k1"]["kernel_ms"]
+            cand = {k: dense[f"sector_k{k}"]["kernel_ms"] for k in ks if k > 1}
+            if cand:
+                kb = min(cand, key=cand.get)
+                dense["best"] = {"best_k": kb, "best_ms": cand[kb], "ratio_to_k1": cand[kb] / t1}
+        dense["workload"] = (f"{dd.B} random starts, n=1000, R=34.4 (seed 3); sector batches, one "
+                             f"dense FP32 inverse-Hessian matrix per batch (Eq. 8-11)")
     whole = descent_params(P, a.max_iter).c()
     x.copy_(x0)
     wws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device=dev)
@@ -120,7 +163,7 @@ def kbatch_study(P, a, dev, stream):
     return {"workload": f"{d.B} random starts, n=1000, R=34.4 (seed 3); k equal batches of each "
                         f"partition visited in order, one L-BFGS iteration per visit; cutoff 2.3 "
                         f"with skin 0.15, or ANM with l_cut 4",
-            "settings": table, "best_k_by_partition": summary,
+            "settings": table, "best_k_by_partition": summary, "dense_bfgs": dense,
             "whole_instance_descent_ms": e0.elapsed_time(e1)}
 
 
@@ -144,6 +187,8 @@ def parse():
     ap.add_argument("--no-sed", action="store_true", help="skip the SED chains")
     ap.add_argument("--no-kbatch", action="store_true", help="skip the k-batch partition study")
     ap.add_argument("--kbatch-ks", default="1,2,3,5,7,10,15", help="batch counts of the study")
+    ap.add_argument("--kbatch-dense-instances", type=int, default=128,
+                    help="random starts of the dense-matrix study (0: skip)")
     ap.add_argument("--kbatch-instances", type=int, default=512,
                     help="random starts per setting (more than the CUs: the rate reflects the mean)")
     ap.add_argument("--sed-iters", type=int, default=10, help="SED iterations of the chains")

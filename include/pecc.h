@@ -266,6 +266,33 @@ int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t
                             size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * The same k-batch descent with the paper's dense inverse-Hessian
+ * approximation of every batch (Eq. 8-11) instead of the limited-memory
+ * history: H_p = I at the start; a visit moves along p = -H_p g(x_p) with
+ * the backtracking line search (alpha0 = 1 once H_p has been updated,
+ * 1/max(1, ||g||) before) and, when s'y > eps_curv y'y, applies Eq. 11
+ *     H_p <- (I - s y'/beta) H_p (I - y s'/beta) + s s'/beta,  beta = y's,
+ * as H_p - (w s' + s w')/beta + (y'w/beta^2 + 1/beta) s s' with w = H_p y.
+ * A direction with g'p >= 0 resets H_p to I.  FP32 matrices of
+ * (2|B_p|)^2 floats live in the workspace (per instance at most
+ * 4 * max_batch * max_n floats, max_batch >= every batch's size; an
+ * instance whose batches need more reports PECC_STATUS_BAD_INSTANCE).
+ * Each visit reads H_p twice and writes it once when it updates: the
+ * memory traffic per outer iteration falls as 1/k, which is where the
+ * paper's batching gains.  One batch (k = 1) is dense BFGS on the whole
+ * instance.  Other arguments, stop tests and results as
+ * pecc_gbo_kbatch_descend (params->m only caps the update count that
+ * selects alpha0).  The workspace must be 256-byte aligned.
+ * ------------------------------------------------------------------------ */
+int pecc_gbo_kbatch_bfgs_workspace_size(const pecc_instances *inst, int32_t max_batch,
+                                        size_t *bytes /*host*/);
+int pecc_gbo_kbatch_bfgs_descend(const pecc_instances *inst, float *xy, const int32_t *batch_of,
+                                 int32_t k, int32_t anm, int32_t max_batch,
+                                 const pecc_descent_params *params /*host*/,
+                                 pecc_descent_result *out /*device [B]*/, void *workspace,
+                                 size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * FP64 feasibility check of Eq. 1-2 through the energy of Def. 3.2 with
  * unit circles: every pair i<j of each instance is enumerated (no list),
  * in FP64 on the FP32 positions.  Per instance: energy64 = E,

@@ -84,6 +84,11 @@ _sig = {
     "pecc_gbo_kbatch_descend_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_gbo_kbatch_descend": (C.c_int, [_P(pecc_instances), _V, _V, C.c_int32, C.c_int32,
                                           _P(pecc_descent_params), _V, _V, C.c_size_t, _V]),
+    "pecc_gbo_kbatch_bfgs_workspace_size": (C.c_int, [_P(pecc_instances), C.c_int32,
+                                                      _P(C.c_size_t)]),
+    "pecc_gbo_kbatch_bfgs_descend": (C.c_int, [_P(pecc_instances), _V, _V, C.c_int32, C.c_int32,
+                                               C.c_int32, _P(pecc_descent_params), _V, _V,
+                                               C.c_size_t, _V]),
     "pecc_adjust_container_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_adjust_container": (C.c_int, [_P(pecc_instances), _V, _P(pecc_descent_params), C.c_float,
                                         C.c_int32, _V, _V, _V, C.c_size_t, _V]),
@@ -346,6 +351,38 @@ def gbo_kbatch_descend(inst: DeviceInstances, xy: torch.Tensor, batch_of: torch.
         workspace = torch.empty(pecc_gbo_kbatch_descend_workspace_size(inst), dtype=torch.uint8,
                                 device=xy.device)
     pecc_gbo_kbatch_descend(inst, xy, batch_of, k, 1 if anm else 0, P, out, workspace)
+    return out
+
+
+def pecc_gbo_kbatch_bfgs_workspace_size(inst: DeviceInstances, max_batch: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.pecc_gbo_kbatch_bfgs_workspace_size(C.byref(inst.c()), int(max_batch), C.byref(b)))
+    return b.value
+
+
+def pecc_gbo_kbatch_bfgs_descend(inst, xy, batch_of, k: int, anm: int, max_batch: int,
+                                 params: pecc_descent_params, out, workspace, stream=None):
+    _check(_lib.pecc_gbo_kbatch_bfgs_descend(C.byref(inst.c()), _ptr(xy), _ptr(batch_of), int(k),
+                                             int(anm), int(max_batch), C.byref(params), _ptr(out),
+                                             _ptr(workspace),
+                                             workspace.numel() * workspace.element_size(),
+                                             _stream(stream)))
+
+
+def gbo_kbatch_bfgs_descend(inst: DeviceInstances, xy: torch.Tensor, batch_of: torch.Tensor,
+                            k: int, max_batch: int, params: DescentParams | None = None,
+                            anm: bool = False, workspace: torch.Tensor | None = None,
+                            out: torch.Tensor | None = None):
+    """The k-batch descent with dense per-batch BFGS matrices (Eq. 8-11), in
+    place; max_batch bounds every batch's size.  Returns the result buffer."""
+    P = (params or DescentParams()).c()
+    if out is None:
+        out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=xy.device)
+    if workspace is None:
+        workspace = torch.empty(pecc_gbo_kbatch_bfgs_workspace_size(inst, max_batch),
+                                dtype=torch.uint8, device=xy.device)
+    pecc_gbo_kbatch_bfgs_descend(inst, xy, batch_of, k, 1 if anm else 0, max_batch, P, out,
+                                 workspace)
     return out
 
 

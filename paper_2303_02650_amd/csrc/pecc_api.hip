@@ -176,6 +176,7 @@ int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs
     a->rounds = 0;
     a->nbat = 1;
     a->anm = 0;
+    a->hstride = 0;
     return PECC_OK;
 }
 
@@ -285,6 +286,68 @@ int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t
     return check_hip(pecc::launch_seq(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
                                       inst->total_n, a, batch_of, out, (int32_t *)workspace, grid,
                                       stream),
+                     fn);
+}
+
+namespace {
+// floats of matrix storage per instance for batches of at most max_batch
+// circles: sum_p d_p^2 <= (2 max_batch) sum_p d_p <= 4 max_batch max_n
+int64_t dense_stride(const pecc_instances *inst, int32_t max_batch)
+{
+    return 4 * (int64_t)max_batch * (int64_t)(inst->max_n > 0 ? inst->max_n : 1);
+}
+}  // namespace
+
+int pecc_gbo_kbatch_bfgs_workspace_size(const pecc_instances *inst, int32_t max_batch,
+                                        size_t *bytes)
+{
+    const char *fn = "pecc_gbo_kbatch_bfgs_workspace_size";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!bytes) return fail(PECC_ERR_INVALID, "%s: bytes is NULL", fn);
+    if (max_batch < 1 || max_batch > PECC_MAX_N)
+        return fail(PECC_ERR_INVALID, "%s: max_batch = %d outside [1, %d]", fn, max_batch, PECC_MAX_N);
+    size_t q = 0;
+    pecc_lbfgs_descend_workspace_size(inst, &q);
+    *bytes = q + align256(sizeof(float) * (size_t)dense_stride(inst, max_batch) *
+                          (size_t)inst->num_instances);
+    return PECC_OK;
+}
+
+int pecc_gbo_kbatch_bfgs_descend(const pecc_instances *inst, float *xy, const int32_t *batch_of,
+                                 int32_t k, int32_t anm, int32_t max_batch,
+                                 const pecc_descent_params *p, pecc_descent_result *out,
+                                 void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    const char *fn = "pecc_gbo_kbatch_bfgs_descend";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && (!xy || !batch_of))
+        return fail(PECC_ERR_INVALID, "%s: xy and batch_of must be set", fn);
+    if (k < 1 || k > PECC_MAX_BATCHES)
+        return fail(PECC_ERR_INVALID, "%s: k = %d outside [1, %d]", fn, k, PECC_MAX_BATCHES);
+    if (anm != 0 && anm != 1) return fail(PECC_ERR_INVALID, "%s: anm must be 0 or 1", fn);
+    size_t need = 0;
+    rc = pecc_gbo_kbatch_bfgs_workspace_size(inst, max_batch, &need);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < need)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(PECC_ERR_WORKSPACE, "%s: workspace must be 256-byte aligned", fn);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
+    a.nbat = k;
+    a.anm = anm;
+    a.hstride = dense_stride(inst, max_batch);
+    size_t q = 0;
+    pecc_lbfgs_descend_workspace_size(inst, &q);
+    float *H = reinterpret_cast<float *>(static_cast<char *>(workspace) + q);
+    const int grid = pecc::descend_grid(inst->num_instances);
+    return check_hip(pecc::launch_dense(inst->offset, inst->R, inst->R64, xy, inst->num_instances,
+                                        inst->total_n, a, batch_of, H, out, (int32_t *)workspace,
+                                        grid, stream),
                      fn);
 }
 

@@ -37,7 +37,7 @@ constexpr int kCPT = kMaxN / kDB;         // circles per thread
 constexpr int kEll = 24;                  // neighbor slots per circle (ELL list)
 constexpr int kEllSeq = 32;               // ... in the batch descent (l_cut up to 4)
 
-enum : int { kModeWhole = 0, kModeAdj = 1, kModeSeq = 2 };
+enum : int { kModeWhole = 0, kModeAdj = 1, kModeSeq = 2, kModeDense = 3 };
 
 template <int ELL>
 struct DescentShared {
@@ -64,6 +64,17 @@ struct SeqShared {
     float BmP[kMaxSeqBatches][kNB * kNB];
     uint8_t bat[kMaxN];
     int cnt[kMaxSeqBatches];
+};
+// Dense batch descent: batch ids and sizes, every circle's index inside its
+// batch, each batch's matrix offset, three vectors of a batch's
+// coordinates, per-wave partial sums.
+struct DenseShared {
+    uint8_t bat[kMaxN];
+    int cnt[kMaxSeqBatches];
+    uint16_t memb[kMaxN];
+    int hoff[kMaxSeqBatches + 1];
+    float vb[3][2 * kMaxN];
+    float wpart[kDB / kWave];
 };
 struct NoShared {
     int unused;
@@ -106,13 +117,15 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ Rv,
     const double *__restrict__ Rv64, float *__restrict__ xy,
     int B, int64_t total_n, DescentArgs A, DescentResultDev *__restrict__ out,
-    int32_t *__restrict__ queue, float *__restrict__ Rout, const int32_t *__restrict__ part)
+    int32_t *__restrict__ queue, float *__restrict__ Rout, const int32_t *__restrict__ part,
+    float *__restrict__ Hws)
 {
     constexpr bool ADJ = MODE == kModeAdj;
-    constexpr bool SEQ = MODE == kModeSeq;
+    constexpr bool DENSE = MODE == kModeDense;
+    constexpr bool SEQ = MODE == kModeSeq || DENSE;
     constexpr int ELL = SEQ ? kEllSeq : kEll;
     __shared__ DescentShared<ELL> sh;
-    __shared__ std::conditional_t<SEQ, SeqShared, NoShared> sq;
+    __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid / kWave;
@@ -155,8 +168,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         int first_b = 0;                // first non-empty batch
         if constexpr (SEQ) {
             for (int q = tid; q < kMaxSeqBatches; q += kDB) sq.cnt[q] = 0;
-            for (int q = tid; q < kMaxSeqBatches * kNB * kNB; q += kDB)
-                sq.BmP[q / (kNB * kNB)][q % (kNB * kNB)] = 0.f;
+            if constexpr (!DENSE)
+                for (int q = tid; q < kMaxSeqBatches * kNB * kNB; q += kDB)
+                    sq.BmP[q / (kNB * kNB)][q % (kNB * kNB)] = 0.f;
             __syncthreads();
             int bad = 0;
 #pragma unroll
@@ -190,6 +204,49 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (sq.cnt[q] > 0) { ++ne; if (first_b < 0) first_b = q; }
             if (first_b < 0) first_b = 0;
             visits = ne > 1;
+        }
+        // dense: every circle's index inside its batch (ascending circle
+        // index), the batches' matrices H_p = I in this instance's region
+        float *Hbase = nullptr;
+        if constexpr (DENSE) {
+            visits = true;                   // one batch too: the dense update
+            Hbase = Hws + (int64_t)b * A.hstride;
+#pragma unroll
+            for (int c = 0; c < kCPT; ++c) {
+                const int i = tid + c * kDB;
+                if (i < n) {
+                    int r = 0;
+                    for (int j = 0; j < i; ++j) r += sq.bat[j] == batc[c] ? 1 : 0;
+                    sq.memb[i] = (uint16_t)r;
+                }
+            }
+            if (tid == 0) {
+                int o = 0;
+                for (int q = 0; q < A.nbat; ++q) {
+                    sq.hoff[q] = o;
+                    const int d = 2 * sq.cnt[q];
+                    o += d * d;
+                }
+                sq.hoff[A.nbat] = o;
+            }
+            __syncthreads();
+            if ((int64_t)sq.hoff[A.nbat] > A.hstride) {
+                if (tid == 0) {
+                    DescentResultDev r = {};
+                    r.status = 7;  // BAD_INSTANCE: the matrices do not fit the workspace
+                    r.E32 = __builtin_nanf("");
+                    r.gnorm = __builtin_nanf("");
+                    r.E64 = -1.0;
+                    out[b] = r;
+                }
+                continue;
+            }
+            for (int q = 0; q < A.nbat; ++q) {
+                const int d = 2 * sq.cnt[q];
+                float *H = Hbase + sq.hoff[q];
+                for (int e = tid; e < d * d; e += kDB) H[e] = (e / d == e % d) ? 1.f : 0.f;
+            }
+            __syncthreads();
         }
 
         // ---- per-thread state (circle c of this thread is tid + c*kDB) ----
@@ -243,7 +300,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // batch descent: batch bb's saved Gram matrix into B (every wave
         // writes the same values and reads back its own)
         auto load_gram = [&](int bb) {
-            if constexpr (SEQ) {
+            if constexpr (SEQ && !DENSE) {
                 const int ln = (int)threadIdx.x & (kWave - 1);
 #pragma unroll
                 for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
@@ -296,6 +353,114 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 anm_len *= 2;
             }
             return changed;
+        };
+        // dense batch descent (Eq. 8-11).  A thread owns rows r = tid,
+        // tid + 512, ... of H_p and reads them as columns (H_p is symmetric),
+        // so every wave's loads are consecutive floats; sums over a batch's
+        // coordinates go lane 0 -> per-wave slot -> every thread in wave
+        // order (deterministic).
+        auto batch_sum = [&](float v) -> float {
+            const int t0 = (int)threadIdx.x;
+            const float w = wave_sum(v);
+            if constexpr (DENSE) {
+                if ((t0 & (kWave - 1)) == 0) sq.wpart[t0 / kWave] = w;
+                __syncthreads();
+                float tsum = 0.f;
+#pragma unroll
+                for (int q = 0; q < kDW; ++q) tsum += sq.wpart[q];
+                __syncthreads();
+                return tsum;
+            } else {
+                return w;
+            }
+        };
+        // stage the batch's components of two per-circle vectors into vb[0], vb[1]
+        auto dense_stage = [&](const float2 (&u)[kCPT], const float2 (&v)[kCPT]) {
+            if constexpr (DENSE) {
+                const int t0 = (int)threadIdx.x;
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    const int i = t0 + c * kDB;
+                    if (act[c] && batc[c] == cb) {
+                        const int m = sq.memb[i];
+                        sq.vb[0][2 * m] = u[c].x;
+                        sq.vb[0][2 * m + 1] = u[c].y;
+                        sq.vb[1][2 * m] = v[c].x;
+                        sq.vb[1][2 * m + 1] = v[c].y;
+                    }
+                }
+                __syncthreads();
+            }
+        };
+        // p = -H_p g on the batch's circles (zero elsewhere); returns g'p
+        auto dense_direction = [&]() -> float {
+            float gpv = 0.f;
+            if constexpr (DENSE) {
+                const int t0 = (int)threadIdx.x;
+                const int d = 2 * sq.cnt[cb];
+                const float *H = Hbase + sq.hoff[cb];
+                dense_stage(g, g);
+                float part = 0.f;
+                for (int r = t0; r < d; r += kDB) {
+                    float acc = 0.f;
+#pragma unroll 8
+                    for (int q = 0; q < d; ++q) acc += H[(int64_t)q * d + r] * sq.vb[0][q];
+                    sq.vb[2][r] = acc;
+                    part += acc * sq.vb[0][r];
+                }
+                gpv = -batch_sum(part);      // its barriers also publish vb[2]
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    const int i = t0 + c * kDB;
+                    if (act[c] && batc[c] == cb) {
+                        const int m = sq.memb[i];
+                        p[c] = make_float2(-sq.vb[2][2 * m], -sq.vb[2][2 * m + 1]);
+                    } else {
+                        p[c] = make_float2(0.f, 0.f);
+                    }
+                }
+            }
+            return gpv;
+        };
+        // Eq. 11 with u = s, v = y, beta = s'y:
+        //   H <- H - (w s' + s w')/beta + (y'w/beta^2 + 1/beta) s s',  w = H y
+        auto dense_update = [&](float beta, const float2 (&s_)[kCPT], const float2 (&y_)[kCPT]) {
+            if constexpr (DENSE) {
+                const int t0 = (int)threadIdx.x;
+                const int d = 2 * sq.cnt[cb];
+                float *H = Hbase + sq.hoff[cb];
+                dense_stage(s_, y_);
+                float part = 0.f;
+                for (int r = t0; r < d; r += kDB) {
+                    float acc = 0.f;
+#pragma unroll 8
+                    for (int q = 0; q < d; ++q) acc += H[(int64_t)q * d + r] * sq.vb[1][q];
+                    sq.vb[2][r] = acc;
+                    part += acc * sq.vb[1][r];
+                }
+                const float yw = batch_sum(part);
+                const float ib = 1.f / beta;
+                const float a2 = yw * ib * ib + ib;
+                for (int r = t0; r < d; r += kDB) {
+                    const float sr = sq.vb[0][r], wr = sq.vb[2][r];
+#pragma unroll 8
+                    for (int q = 0; q < d; ++q) {
+                        const float sq_ = sq.vb[0][q], wq = sq.vb[2][q];
+                        float &h = H[(int64_t)q * d + r];
+                        h = h - (wq * sr + sq_ * wr) * ib + a2 * sq_ * sr;
+                    }
+                }
+                __syncthreads();
+            }
+        };
+        auto dense_reset = [&]() {
+            if constexpr (DENSE) {
+                const int d = 2 * sq.cnt[cb];
+                float *H = Hbase + sq.hoff[cb];
+                __syncthreads();
+                for (int e = (int)threadIdx.x; e < d * d; e += kDB) H[e] = (e / d == e % d) ? 1.f : 0.f;
+                __syncthreads();
+            }
         };
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
@@ -652,7 +817,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
-                    if (push && inb[c]) {
+                    if (!DENSE && push && inb[c]) {
 #pragma unroll
                         for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
                         S[kMM - 1][c] = sc[c];
@@ -694,13 +859,17 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     // ---- end of a visit: save the batch's Gram matrix (every
                     // wave has finished with B), then the next batch
                     kb_v = lane == cb ? k : kb_v;
-                    __syncthreads();
+                    if constexpr (DENSE) {
+                        if (push) dense_update(lane_value(tot, sScYc), sc, yc);
+                    } else {
+                        __syncthreads();
 #pragma unroll
-                    for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
-                        const int ent = lane + kWave * r;
-                        if (ent < kNB * kNB) sq.BmP[cb][ent] = sh.Bm[cur][ent];
+                        for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
+                            const int ent = lane + kWave * r;
+                            if (ent < kNB * kNB) sq.BmP[cb][ent] = sh.Bm[cur][ent];
+                        }
+                        __syncthreads();
                     }
-                    __syncthreads();
                     int nx = cb + 1;
                     while (nx < A.nbat && sq.cnt[nx] == 0) ++nx;
                     if (nx >= A.nbat) {           // outer iteration done
@@ -741,74 +910,80 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (it >= A.max_iter) { status = 5; break; }
             }
 
-            // ================= direction: two-loop recursion on B ===============
-            // Lane l holds row l of B (the basis s_0..s_9, y_0..y_9, g), so
-            // acc = (B c) for the current coefficient vector c is one FMA per
-            // lane per step: q = g - sum_i a_i y_i gives acc -= a_j B[l][y_j],
-            // r = gamma q + sum_j (a_j - b_j) s_j gives acc += (a_j - b_j) B[l][s_j].
-            // s_j'q and y_j'r are then single lanes of acc (one readlane per
-            // step).  The per-pair scalars stay lane-indexed in VGPRs (lane j:
-            // rho_j, a_j, the s_j coefficient; lane 10 + j: rho_j and a_j again)
-            // and are read out only where the direction is formed.
-            float Bc[kNB];
-#pragma unroll
-            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
-            const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
-            const bool live = lane < 2 * kMM && jp >= kMM - k;
-            const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
-            const float rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
-            float acc = Bc[kG];                                   // (B q)_l with q = g
-            float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
-#pragma unroll
-            for (int j = kMM - 1; j >= 0; --j) {
-                if (j >= kMM - k) {
-                    const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
-                    if (jp == j) alph_v = a;
-                    acc -= a * Bc[kMM + j];
-                }
-            }
-            float gam = 1.f;
-            if (k > 0) {
-                const float sy = lane_value(Bc[kMM - 1], 2 * kMM - 1);
-                const float yy = lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
-                gam = sy / yy;
-            }
-            acc *= gam;                                           // (B r)_l with r = gamma q
-            float cs_v = 0.f;                                     // coefficient of s_j at lane j
-#pragma unroll
-            for (int j = 0; j < kMM; ++j) {
-                if (j >= kMM - k) {
-                    const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
-                    if (lane == j) cs_v = c;
-                    acc += c * Bc[j];
-                }
-            }
-            {
-                gp = -lane_value(acc, kG);                        // g'p = -g'r
-                const float cy_v = -gam * alph_v;                 // coefficient of y_j at lane j
-#pragma unroll
-                for (int c = 0; c < kCPT; ++c) {
-                    float px = -gam * g[c].x, py = -gam * g[c].y;
-#pragma unroll
-                    for (int j = 0; j < kMM; ++j) {
-                        const float csj = lane_value(cs_v, j), cyj = lane_value(cy_v, j);
-                        px -= csj * S[j][c].x + cyj * Y[j][c].x;
-                        py -= csj * S[j][c].y + cyj * Y[j][c].y;
+            if constexpr (DENSE) {
+                // ================= direction: p = -H_p g (Eq. 8) ==================
+                gp = dense_direction();
+            } else {
+                // ================= direction: two-loop recursion on B ===============
+                // Lane l holds row l of B (the basis s_0..s_9, y_0..y_9, g), so
+                // acc = (B c) for the current coefficient vector c is one FMA per
+                // lane per step: q = g - sum_i a_i y_i gives acc -= a_j B[l][y_j],
+                // r = gamma q + sum_j (a_j - b_j) s_j gives acc += (a_j - b_j) B[l][s_j].
+                // s_j'q and y_j'r are then single lanes of acc (one readlane per
+                // step).  The per-pair scalars stay lane-indexed in VGPRs (lane j:
+                // rho_j, a_j, the s_j coefficient; lane 10 + j: rho_j and a_j again)
+                // and are read out only where the direction is formed.
+                float Bc[kNB];
+    #pragma unroll
+                for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
+                const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
+                const bool live = lane < 2 * kMM && jp >= kMM - k;
+                const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
+                const float rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
+                float acc = Bc[kG];                                   // (B q)_l with q = g
+                float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
+    #pragma unroll
+                for (int j = kMM - 1; j >= 0; --j) {
+                    if (j >= kMM - k) {
+                        const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
+                        if (jp == j) alph_v = a;
+                        acc -= a * Bc[kMM + j];
                     }
-                    p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(px, py)
-                                                              : make_float2(0.f, 0.f);
                 }
-                if constexpr (ADJ) {
-                    float pr = -gam * gR;
-#pragma unroll
-                    for (int j = 0; j < kMM; ++j)
-                        pr -= lane_value(cs_v, j) * lane_value(hR_v, j) +
-                              lane_value(cy_v, j) * lane_value(hR_v, kMM + j);
-                    pR = pr;
+                float gam = 1.f;
+                if (k > 0) {
+                    const float sy = lane_value(Bc[kMM - 1], 2 * kMM - 1);
+                    const float yy = lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
+                    gam = sy / yy;
+                }
+                acc *= gam;                                           // (B r)_l with r = gamma q
+                float cs_v = 0.f;                                     // coefficient of s_j at lane j
+    #pragma unroll
+                for (int j = 0; j < kMM; ++j) {
+                    if (j >= kMM - k) {
+                        const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
+                        if (lane == j) cs_v = c;
+                        acc += c * Bc[j];
+                    }
+                }
+                {
+                    gp = -lane_value(acc, kG);                        // g'p = -g'r
+                    const float cy_v = -gam * alph_v;                 // coefficient of y_j at lane j
+    #pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        float px = -gam * g[c].x, py = -gam * g[c].y;
+    #pragma unroll
+                        for (int j = 0; j < kMM; ++j) {
+                            const float csj = lane_value(cs_v, j), cyj = lane_value(cy_v, j);
+                            px -= csj * S[j][c].x + cyj * Y[j][c].x;
+                            py -= csj * S[j][c].y + cyj * Y[j][c].y;
+                        }
+                        p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(px, py)
+                                                                  : make_float2(0.f, 0.f);
+                    }
+                    if constexpr (ADJ) {
+                        float pr = -gam * gR;
+    #pragma unroll
+                        for (int j = 0; j < kMM; ++j)
+                            pr -= lane_value(cs_v, j) * lane_value(hR_v, j) +
+                                  lane_value(cy_v, j) * lane_value(hR_v, kMM + j);
+                        pR = pr;
+                    }
                 }
             }
             if (k > 0 && !(gp < 0.f)) {
                 k = 0;
+                if constexpr (DENSE) dense_reset();
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c)
                     p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(-g[c].x, -g[c].y)
@@ -919,7 +1094,7 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
     if (grid < 1) grid = 1;
     lbfgs_descend_kernel<kModeWhole><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
                                                           reinterpret_cast<DescentResultDev *>(out),
-                                                          queue, nullptr, nullptr);
+                                                          queue, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -931,7 +1106,7 @@ hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B
     if (grid < 1) grid = 1;
     lbfgs_descend_kernel<kModeAdj><<<grid, kDB, 0, s>>>(offset, R, nullptr, xy, B, total_n, a,
                                                         reinterpret_cast<DescentResultDev *>(out),
-                                                        queue, Rout, nullptr);
+                                                        queue, Rout, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -943,7 +1118,19 @@ hipError_t launch_seq(const int32_t *offset, const float *R, const double *R64, 
     if (grid < 1) grid = 1;
     lbfgs_descend_kernel<kModeSeq><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
                                                         reinterpret_cast<DescentResultDev *>(out),
-                                                        queue, nullptr, batch_of);
+                                                        queue, nullptr, batch_of, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(const int32_t *offset, const float *R, const double *R64, float *xy,
+                        int B, int64_t total_n, const DescentArgs &a, const int32_t *batch_of,
+                        float *H, void *out, int32_t *queue, int grid, hipStream_t s)
+{
+    queue_init_kernel<<<1, kQB, 0, s>>>(offset, B, queue);
+    if (grid < 1) grid = 1;
+    lbfgs_descend_kernel<kModeDense><<<grid, kDB, 0, s>>>(offset, R, R64, xy, B, total_n, a,
+                                                          reinterpret_cast<DescentResultDev *>(out),
+                                                          queue, nullptr, batch_of, H);
     return hipGetLastError();
 }
 

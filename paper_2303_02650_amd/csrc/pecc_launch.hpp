@@ -28,6 +28,7 @@ struct DescentArgs {
     int rounds;       // container adjustment: minimisations, lambda halved after each
     int nbat;         // batch descent: batches of the partition (1..kMaxSeqBatches)
     int anm;          // batch descent: 1 = adaptive neighbor maintenance (Alg. 3)
+    int64_t hstride;  // dense batch descent: floats of matrix storage per instance
 };
 
 constexpr int kMaxSeqBatches = 16;   // batches of the batch descent at most
@@ -51,6 +52,12 @@ hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B
 hipError_t launch_seq(const int32_t *offset, const float *R, const double *R64, float *xy, int B,
                       int64_t total_n, const DescentArgs &a, const int32_t *batch_of, void *out,
                       int32_t *queue, int grid, hipStream_t s);
+
+// Dense batch descent (the paper's per-batch inverse-Hessian matrices,
+// Eq. 8-11): H holds a.hstride floats per instance.
+hipError_t launch_dense(const int32_t *offset, const float *R, const double *R64, float *xy,
+                        int B, int64_t total_n, const DescentArgs &a, const int32_t *batch_of,
+                        float *H, void *out, int32_t *queue, int grid, hipStream_t s);
 
 // k-batch partitions of Sec. 4.1 (kind: 0 sector, 1 annulus, 2 fence, 3 random).
 hipError_t launch_partition(const int32_t *offset, const float *xy, int B, int64_t total_n,

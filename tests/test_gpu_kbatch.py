@@ -199,3 +199,73 @@ def test_bad_batch_ids_and_limits(P):
         P.gbo_kbatch_descend(d, xy, b0, 17)
     with pytest.raises(P.PeccError):
         P.partition(d, xy, "sector", 0)
+
+
+# ---------------------------------------------------------------------------
+# dense per-batch BFGS matrices (Eq. 8-11)
+# ---------------------------------------------------------------------------
+def run_dense(P, inst, batch_of, k, params, max_batch=None, anm=False):
+    d, xy = to_dev(P, inst)
+    bo = torch.from_numpy(np.ascontiguousarray(batch_of, dtype=np.int32)).cuda()
+    mb = max_batch or int(max(np.bincount(batch_of[inst.offset[b]:inst.offset[b + 1]],
+                                          minlength=k).max() for b in range(inst.B)))
+    res = P.results(P.gbo_kbatch_bfgs_descend(d, xy, bo, k, mb, params, anm=anm))
+    return xy.cpu().numpy().reshape(-1, 2), res
+
+
+DENSE_CASES = {
+    "C1-k1": (lambda: synth.C1(), "sector", 1),
+    "C1-k3": (lambda: synth.C1(), "fence", 3),
+    "C4-k5": (lambda: synth.C4(2), "sector", 5),
+    "C3-k7": (lambda: synth.pack([synth.C3_restarts().instance(i) for i in (2, 3)],
+                                 [synth.C3_restarts().R[i] for i in (2, 3)]), "annulus", 7),
+}
+
+
+@pytest.mark.parametrize("name", list(DENSE_CASES))
+@pytest.mark.parametrize("outer", [1, 3])
+def test_dense_first_outer_iterations_follow_oracle(P, name, outer):
+    mk, kind, k = DENSE_CASES[name]
+    inst = mk()
+    bo = host_partition(inst, kind, k)
+    params = P.DescentParams(max_iter=outer, g_tol=0.0, ftol=0.0)
+    xg, res = run_dense(P, inst, bo, k, params)
+    for b in range(inst.B):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_seq_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                             bo[o0:o1], k, oracle.DescentParams(g_tol=0.0),
+                                             max_outer=outer, dense=True)
+        assert res["iters"][b] == r64["outer"] == outer
+        scale = max(1.0, float(np.abs(x64).max()))
+        err = np.abs(xg[o0:o1] - x64).max() / scale
+        assert err < 5e-5 * outer, (name, b, err)
+        assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-3)
+
+
+def test_dense_descents_reach_oracle_outcomes(P):
+    inst = synth.instance_set(16, 20, 5.2, seed=9)            # C1-shaped starts
+    for k in (1, 2):
+        bo = host_partition(inst, "sector", k)
+        params = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4)
+        xg, res = run_dense(P, inst, bo, k, params)
+        again, _ = run_dense(P, inst, bo, k, params)
+        assert np.array_equal(xg, again)
+        feas_gpu = feas_or = 0
+        for b in range(inst.B):
+            o0, o1 = inst.offset[b], inst.offset[b + 1]
+            feas_gpu += oracle.verify(xg[o0:o1], float(inst.R[b]))["E"] < 1e-20
+            _, r64, _ = oracle.gbo_seq_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                               bo[o0:o1], k, oracle.DescentParams(g_tol=1e-12),
+                                               max_outer=2000, dense=True)
+            feas_or += r64["status"] == "FEASIBLE"
+        assert abs(feas_gpu - feas_or) <= 4, (k, feas_gpu, feas_or)
+        assert feas_gpu >= 6
+
+
+def test_dense_workspace_bound(P):
+    inst = synth.C1()
+    bo = host_partition(inst, "sector", 2)                    # batches of 10
+    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=9)
+    assert P.STATUS[res["status"][0]] == "BAD_INSTANCE"
+    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=10)
+    assert P.STATUS[res["status"][0]] != "BAD_INSTANCE"
