@@ -135,9 +135,14 @@ def kbatch_study(P, a, dev, stream):
             torch.cuda.synchronize()
             r = P.results(outd)
             ms = e0.elapsed_time(e1)
+            # matrix bytes: per visit two reads (H g, H y) and one read +
+            # write (Eq. 11), counting every visit as updating its matrix
+            vis = float(r["iters"].astype(np.float64).sum()) * k
+            mbytes = vis * 4 * 4 * (2 * 1000 / k) ** 2
             dense[f"sector_k{k}"] = {
                 "kernel_ms": ms, "descents_per_s": dd.B / (ms / 1e3),
                 "matrix_bytes_per_instance": 4 * k * (2 * mb) ** 2,
+                "matrix_GBs_if_every_visit_updates": mbytes / (ms / 1e3) / 1e9,
                 "outer_iters_mean": float(r["iters"].mean()), "evals_mean": float(r["evals"].mean()),
                 "E64_mean": float(e64d.cpu().numpy().mean()),
                 "feasible_fraction": float(feasd.cpu().numpy().mean()),
@@ -186,8 +191,11 @@ def parse():
     ap.add_argument("--no-adjust", action="store_true", help="skip the container adjustment")
     ap.add_argument("--no-sed", action="store_true", help="skip the SED chains")
     ap.add_argument("--no-kbatch", action="store_true", help="skip the k-batch partition study")
+    ap.add_argument("--tune", action="store_true",
+                    help="main step with the autotuner's list cutoff / skin (default 2.3 / 0.15: "
+                         "the tuner's early-iteration cost does not predict the tail-bound step)")
     ap.add_argument("--kbatch-ks", default="1,2,3,5,7,10,15", help="batch counts of the study")
-    ap.add_argument("--kbatch-dense-instances", type=int, default=128,
+    ap.add_argument("--kbatch-dense-instances", type=int, default=256,
                     help="random starts of the dense-matrix study (0: skip)")
     ap.add_argument("--kbatch-instances", type=int, default=512,
                     help="random starts per setting (more than the CUs: the rate reflects the mean)")
@@ -288,6 +296,17 @@ def main():
     xy0 = torch.from_numpy(inst.xy.reshape(-1)).to(dev)
     xy = torch.empty_like(xy0)
     params = descent_params(P, a.max_iter)
+    main_tune = None
+    if a.tune:
+        # list cutoff / rebuild distance / cell side measured on a 64-start
+        # sample of this workload (cost per iteration; same outcomes)
+        from dataclasses import replace
+        from paper_2303_02650_amd import autotune as AT
+        main_tune = AT.tune_descent(inst.offset, inst.R, inst.xy, params, sample=64, reps=2)
+        tb = main_tune["best"]
+        params = replace(params, cutoff=tb["cutoff"], skin_half=tb["skin_half"],
+                         cell_size=tb["cell_size"])
+        print(f"[bench] main-step autotune: {tb}", file=sys.stderr, flush=True)
     ws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device=dev)
     out = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     e64 = torch.empty(d.B, dtype=torch.float64, device=dev)
@@ -361,8 +380,10 @@ def main():
         "vs_baseline": None, "dtype": "f32 (f64 verify and near-zero line search)",
         "data": "synthetic",
         "config": {"workload": f"{a.batch} random starts, n={N_CIRCLES}, R={R_C2}, m=10, "
-                               f"max_iter={a.max_iter}, cutoff 2.3, skin 0.15",
-                   "instances": a.batch, "n": N_CIRCLES, "R": R_C2},
+                               f"max_iter={a.max_iter}",
+                   "instances": a.batch, "n": N_CIRCLES, "R": R_C2,
+                   "list_cutoff": params.cutoff, "skin_half": params.skin_half,
+                   "cell_size": params.cell_size},
         "pair_evals_per_s": pair_evals / (ms_per_step / 1e3),
         "step_ms_events_median": float(np.median(np.array(desc_ms) + np.array(ver_ms))),
         "descent_ms_events_median": float(np.median(desc_ms)),
@@ -372,6 +393,9 @@ def main():
         "E64_final_mean": float(e64.cpu().numpy().mean()),
         "roofline": roof,
     }
+    if main_tune is not None:
+        line["autotune"] = {"chosen": main_tune["best"], "sample_instances": 64,
+                            "table": main_tune["table"]}
 
     # ---- container adjustment (Alg. 2) of the 256 descended layouts --------
     if not a.no_adjust:

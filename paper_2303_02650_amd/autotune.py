@@ -38,7 +38,7 @@ from . import (DescentParams, DeviceInstances, RESULT_DTYPE, pecc_gbo_descend,
 
 # (cutoff, rebuild distance, cell side; 0 = the cutoff)
 DESCENT_CANDIDATES = [(2.3, 0.15, 0.0), (2.2, 0.10, 0.0), (2.4, 0.20, 0.0), (2.6, 0.30, 0.0),
-                      (2.3, 0.15, 2.9), (2.4, 0.20, 3.0)]
+                      (2.8, 0.40, 0.0), (3.0, 0.50, 0.0), (2.3, 0.15, 2.9), (2.4, 0.20, 3.0)]
 GBO_CANDIDATES = [4, 5, 6]
 
 

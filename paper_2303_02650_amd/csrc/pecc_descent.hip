@@ -75,7 +75,92 @@ struct DenseShared {
     int hoff[kMaxSeqBatches + 1];
     float vb[3][2 * kMaxN];
     float wpart[kDB / kWave];
+    float2 part[kDB];
 };
+
+// Work split of a pass over a symmetric d x d matrix (d even) stored
+// row-major: thread t takes the column pair pr (two consecutive columns, one
+// 8-byte load per row, consecutive across the wave) and, when the pairs are
+// fewer than the threads, a slice of the rows, so every wave streams.
+struct SymSplit {
+    int cp, nq, items;
+    __device__ SymSplit(int d, int nthreads)
+    {
+        cp = d / 2;
+        nq = cp > 0 ? nthreads / cp : 1;
+        nq = nq < 1 ? 1 : (nq > 8 ? 8 : nq);
+        items = (cp < nthreads ? cp : nthreads) * nq;
+    }
+};
+
+// y = H v for a symmetric H (d x d, d even, 8-byte aligned), as column sums:
+// y_r = sum_q H[q][r] v[q] in ascending q per row slice, slices added in
+// order (deterministic).  Every thread of the block calls it; ends with a
+// barrier.
+template <int BLOCK>
+__device__ void sym_matvec(const float *__restrict__ H, int d, const float *v, float *y,
+                           float2 *part)
+{
+    const int t = (int)threadIdx.x;
+    const SymSplit sp(d, BLOCK);
+    const float2 *H2 = reinterpret_cast<const float2 *>(H);
+    for (int base = 0; base < sp.cp; base += BLOCK) {
+        const int pairs = sp.cp - base < BLOCK ? sp.cp - base : BLOCK;
+        const int nq = base == 0 ? sp.nq : 1;
+        if (t < pairs * nq) {
+            const int pr = base + t % pairs, sl = t / pairs;
+            const int q0 = (int)((int64_t)d * sl / nq), q1 = (int)((int64_t)d * (sl + 1) / nq);
+            float ax = 0.f, ay = 0.f;
+#pragma unroll 16
+            for (int q = q0; q < q1; ++q) {
+                const float2 h = H2[(int64_t)q * sp.cp + pr];
+                const float vq = v[q];
+                ax += h.x * vq;
+                ay += h.y * vq;
+            }
+            part[t] = make_float2(ax, ay);
+        }
+        __syncthreads();
+        for (int r = t; r < pairs; r += BLOCK) {
+            float2 a = part[r];
+            for (int j = 1; j < nq; ++j) {
+                a.x += part[j * pairs + r].x;
+                a.y += part[j * pairs + r].y;
+            }
+            y[2 * (base + r)] = a.x;
+            y[2 * (base + r) + 1] = a.y;
+        }
+        __syncthreads();
+    }
+}
+
+// H += -(w s' + s w') ib + a2 s s' (symmetric rank-2 update, same split).
+template <int BLOCK>
+__device__ void sym_rank2(float *__restrict__ H, int d, const float *s, const float *w, float ib,
+                          float a2)
+{
+    const int t = (int)threadIdx.x;
+    const SymSplit sp(d, BLOCK);
+    float2 *H2 = reinterpret_cast<float2 *>(H);
+    for (int base = 0; base < sp.cp; base += BLOCK) {
+        const int pairs = sp.cp - base < BLOCK ? sp.cp - base : BLOCK;
+        const int nq = base == 0 ? sp.nq : 1;
+        if (t < pairs * nq) {
+            const int pr = base + t % pairs, sl = t / pairs;
+            const int q0 = (int)((int64_t)d * sl / nq), q1 = (int)((int64_t)d * (sl + 1) / nq);
+            const float s0 = s[2 * pr], s1 = s[2 * pr + 1], w0 = w[2 * pr], w1 = w[2 * pr + 1];
+#pragma unroll 8
+            for (int q = q0; q < q1; ++q) {
+                const float sq_ = s[q], wq = w[q];
+                float2 h = H2[(int64_t)q * sp.cp + pr];
+                h.x = h.x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
+                h.y = h.y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
+                H2[(int64_t)q * sp.cp + pr] = h;
+            }
+        }
+    }
+    __syncthreads();
+}
 struct NoShared {
     int unused;
 };
@@ -400,15 +485,10 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const int d = 2 * sq.cnt[cb];
                 const float *H = Hbase + sq.hoff[cb];
                 dense_stage(g, g);
+                sym_matvec<kDB>(H, d, sq.vb[0], sq.vb[2], sq.part);
                 float part = 0.f;
-                for (int r = t0; r < d; r += kDB) {
-                    float acc = 0.f;
-#pragma unroll 8
-                    for (int q = 0; q < d; ++q) acc += H[(int64_t)q * d + r] * sq.vb[0][q];
-                    sq.vb[2][r] = acc;
-                    part += acc * sq.vb[0][r];
-                }
-                gpv = -batch_sum(part);      // its barriers also publish vb[2]
+                for (int r = t0; r < d; r += kDB) part += sq.vb[2][r] * sq.vb[0][r];
+                gpv = -batch_sum(part);
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = t0 + c * kDB;
@@ -430,27 +510,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const int d = 2 * sq.cnt[cb];
                 float *H = Hbase + sq.hoff[cb];
                 dense_stage(s_, y_);
+                sym_matvec<kDB>(H, d, sq.vb[1], sq.vb[2], sq.part);
                 float part = 0.f;
-                for (int r = t0; r < d; r += kDB) {
-                    float acc = 0.f;
-#pragma unroll 8
-                    for (int q = 0; q < d; ++q) acc += H[(int64_t)q * d + r] * sq.vb[1][q];
-                    sq.vb[2][r] = acc;
-                    part += acc * sq.vb[1][r];
-                }
+                for (int r = t0; r < d; r += kDB) part += sq.vb[2][r] * sq.vb[1][r];
                 const float yw = batch_sum(part);
                 const float ib = 1.f / beta;
                 const float a2 = yw * ib * ib + ib;
-                for (int r = t0; r < d; r += kDB) {
-                    const float sr = sq.vb[0][r], wr = sq.vb[2][r];
-#pragma unroll 8
-                    for (int q = 0; q < d; ++q) {
-                        const float sq_ = sq.vb[0][q], wq = sq.vb[2][q];
-                        float &h = H[(int64_t)q * d + r];
-                        h = h - (wq * sr + sq_ * wr) * ib + a2 * sq_ * sr;
-                    }
-                }
-                __syncthreads();
+                sym_rank2<kDB>(H, d, sq.vb[0], sq.vb[2], ib, a2);
             }
         };
         auto dense_reset = [&]() {

@@ -269,3 +269,16 @@ def test_dense_workspace_bound(P):
     assert P.STATUS[res["status"][0]] == "BAD_INSTANCE"
     _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=10)
     assert P.STATUS[res["status"][0]] != "BAD_INSTANCE"
+
+
+def test_dense_with_anm_follows_oracle_early(P):
+    inst = synth.C4(1)
+    bo = host_partition(inst, "sector", 5)
+    for outer in (1, 3):
+        params = P.DescentParams(max_iter=outer, g_tol=0.0, ftol=0.0, cutoff=4.0)
+        xg, res = run_dense(P, inst, bo, 5, params, anm=True)
+        x64, r64, _ = oracle.gbo_seq_descend(inst.instance(0).astype(np.float64), inst.R[0], bo, 5,
+                                             oracle.DescentParams(g_tol=0.0), max_outer=outer,
+                                             anm=True, lcut=4.0, dense=True)
+        assert np.abs(xg - x64).max() < 5e-5 * outer * max(1.0, np.abs(x64).max())
+        assert res["rebuilds"][0] == 1 + r64["anm_changes"], outer
