@@ -65,6 +65,7 @@ def kbatch_study(P, a, dev, stream):
     feas = torch.empty(d.B, dtype=torch.int32, device=dev)
     bo = torch.empty(d.total_n, dtype=torch.int32, device=dev)
     ks = [int(v) for v in a.kbatch_ks.split(",") if v]
+    dks = [int(v) for v in a.kbatch_dense_ks.split(",") if v]
 
     def one(kind, k, anm=False):
         prm = descent_params(P, a.max_iter)
@@ -121,7 +122,7 @@ def kbatch_study(P, a, dev, stream):
         e64d = torch.empty(dd.B, dtype=torch.float64, device=dev)
         feasd = torch.empty(dd.B, dtype=torch.int32, device=dev)
         pc = descent_params(P, a.max_iter).c()
-        for k in ks:
+        for k in dks:
             mb = -(-1000 // k)
             wsd = torch.empty(P.pecc_gbo_kbatch_bfgs_workspace_size(dd, mb), dtype=torch.uint8,
                               device=dev)
@@ -149,9 +150,9 @@ def kbatch_study(P, a, dev, stream):
                 "status_counts": {P.STATUS[s]: int((r["status"] == s).sum()) for s in np.unique(r["status"])}}
             del wsd
             print(f"[bench] kbatch dense sector k={k}: {ms:.1f} ms", file=sys.stderr, flush=True)
-        if 1 in ks:
+        if 1 in dks:
             t1 = dense["sector_k1"]["kernel_ms"]
-            cand = {k: dense[f"sector_k{k}"]["kernel_ms"] for k in ks if k > 1}
+            cand = {k: dense[f"sector_k{k}"]["kernel_ms"] for k in dks if k > 1}
             if cand:
                 kb = min(cand, key=cand.get)
                 dense["best"] = {"best_k": kb, "best_ms": cand[kb], "ratio_to_k1": cand[kb] / t1}
@@ -195,6 +196,7 @@ def parse():
                     help="main step with the autotuner's list cutoff / skin (default 2.3 / 0.15: "
                          "the tuner's early-iteration cost does not predict the tail-bound step)")
     ap.add_argument("--kbatch-ks", default="1,2,3,5,7,10,15", help="batch counts of the study")
+    ap.add_argument("--kbatch-dense-ks", default="1,2,5,10", help="batch counts, dense matrices")
     ap.add_argument("--kbatch-dense-instances", type=int, default=256,
                     help="random starts of the dense-matrix study (0: skip)")
     ap.add_argument("--kbatch-instances", type=int, default=512,
