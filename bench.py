@@ -192,6 +192,9 @@ def parse():
     ap.add_argument("--no-adjust", action="store_true", help="skip the container adjustment")
     ap.add_argument("--no-sed", action="store_true", help="skip the SED chains")
     ap.add_argument("--no-kbatch", action="store_true", help="skip the k-batch partition study")
+    ap.add_argument("--no-framework", action="store_true", help="skip the Alg. 4 framework runs")
+    ap.add_argument("--framework-rounds", type=int, default=3)
+    ap.add_argument("--framework-sed-iters", type=int, default=10)
     ap.add_argument("--tune", action="store_true",
                     help="main step with the autotuner's list cutoff / skin (default 2.3 / 0.15: "
                          "the tuner's early-iteration cost does not predict the tail-bound step)")
@@ -708,6 +711,29 @@ def main():
         line["sed"]["mean_descents_to_first_feasible"] = float(ff[ff > 0].mean()) if (ff > 0).any() else None
         print(f"[bench] sed: {line['sed']}", file=sys.stderr, flush=True)
         del ch
+
+    # ---- the framework of Alg. 4: 64 runs of n = 1000 ----------------------
+    if not a.no_framework:
+        from paper_2303_02650_amd.framework import Framework
+        Rb = float(np.sqrt(1000 / 0.85))
+        t0 = time.perf_counter()
+        fw = Framework(1000, [Rb] * 64, descent_params(P, a.max_iter), M=25,
+                       s_iter=a.framework_sed_iters, seed=23)
+        t_init = time.perf_counter() - t0
+        info = fw.run(rounds=a.framework_rounds)
+        Rbest = np.array(info["R_best"])
+        line["framework"] = {
+            "workload": f"64 runs of n=1000, reference radius R_b = sqrt(1000/0.85) = {Rb:.4f} "
+                        f"(a synthetic stand-in: density 0.85), {a.framework_rounds} rounds of SED "
+                        f"({a.framework_sed_iters} iterations, M=25) + container adjustment",
+            "seconds_initial": t_init, "seconds_rounds": info["seconds"],
+            "R_initial_mean": float(np.mean(info["R_initial"])),
+            "R_best_mean": float(Rbest.mean()), "R_best_min": float(Rbest.min()),
+            "density_best_mean": float(np.mean(1000 / Rbest ** 2)),
+            "below_R_b_fraction": float((Rbest < Rb).mean()),
+            "history": info["history"]}
+        print(f"[bench] framework: R {np.mean(info['R_initial']):.4f} -> {Rbest.mean():.4f} "
+              f"(min {Rbest.min():.4f}) in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
 
     # ---- standalone list sweep at an HBM-sized batch -----------------------
     if not a.no_sweep:

@@ -112,3 +112,36 @@ def test_train_step_graph_replays_advance_like_eager(P):
     assert T.step.item() == 3
     assert torch.equal(T.params, eager.params) and torch.equal(T.m, eager.m)
     assert torch.equal(T.v, eager.v)
+
+
+def test_partition_and_kbatch_descents_graph_replays(P):
+    inst = synth.C1()
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    x0 = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    x_l, x_d = torch.empty_like(x0), torch.empty_like(x0)
+    bo = torch.empty(d.total_n, dtype=torch.int32, device="cuda")
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4).c()
+    ws_l = torch.empty(P.pecc_gbo_kbatch_descend_workspace_size(d), dtype=torch.uint8, device="cuda")
+    ws_d = torch.empty(P.pecc_gbo_kbatch_bfgs_workspace_size(d, 7), dtype=torch.uint8, device="cuda")
+    out_l = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    out_d = torch.empty_like(out_l)
+
+    def step():
+        P.pecc_partition(d, x0, P.PARTITIONS["sector"], 3, 0, bo)
+        x_l.copy_(x0)
+        x_d.copy_(x0)
+        P.pecc_gbo_kbatch_descend(d, x_l, bo, 3, 0, prm, out_l, ws_l)
+        P.pecc_gbo_kbatch_bfgs_descend(d, x_d, bo, 3, 0, 7, prm, out_d, ws_d)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (bo.clone(), x_l.clone(), out_l.clone(), x_d.clone(), out_d.clone())
+    g = capture(step)
+    for rep in range(3):
+        bo.fill_(-1); x_l.zero_(); x_d.zero_(); out_l.zero_(); out_d.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((bo, x_l, out_l, x_d, out_d), ref):
+            assert torch.equal(a, b), rep
+        P.partition(d, x0, "fence", 2)                   # eager work between replays
+        torch.cuda.synchronize()
