@@ -75,28 +75,61 @@ struct DenseShared {
     int hoff[kMaxSeqBatches + 1];
     float vb[3][2 * kMaxN];
     float wpart[kDB / kWave];
-    float2 part[kDB];
+    float2 part[2 * kDB];
 };
 
-// Work split of a pass over a symmetric d x d matrix (d even) stored
-// row-major: thread t takes the column pair pr (two consecutive columns, one
-// 8-byte load per row, consecutive across the wave) and, when the pairs are
-// fewer than the threads, a slice of the rows, so every wave streams.
+// Work split of a pass over a symmetric d x d matrix (d even, d <= 2048)
+// stored row-major: an item is a column pair pr (two consecutive columns,
+// one 8-byte load per row, consecutive across a wave) and a slice of the
+// rows; there are up to 2 BLOCK items and thread t streams items t and
+// t + BLOCK side by side, so every wave keeps two load streams in flight.
 struct SymSplit {
     int cp, nq, items;
     __device__ SymSplit(int d, int nthreads)
     {
         cp = d / 2;
-        nq = cp > 0 ? nthreads / cp : 1;
-        nq = nq < 1 ? 1 : (nq > 8 ? 8 : nq);
-        items = (cp < nthreads ? cp : nthreads) * nq;
+        nq = cp > 0 ? 2 * nthreads / cp : 1;
+        nq = nq < 1 ? 1 : (nq > 16 ? 16 : nq);
+        items = cp * nq;
+    }
+    __device__ void item(int it, int d, int &pr, int &q0, int &q1) const
+    {
+        if (it >= items) { pr = 0; q0 = q1 = 0; return; }
+        pr = it % cp;
+        const int sl = it / cp;
+        q0 = (int)((int64_t)d * sl / nq);
+        q1 = (int)((int64_t)d * (sl + 1) / nq);
     }
 };
 
+// Column-pair dot product of rows [q, q + len) of one item: batches of 8
+// independent loads, then the FMAs (rows ascending).
+__device__ __forceinline__ void col_dot(const float2 *__restrict__ col, int64_t stride,
+                                        const float *v, int len, float &ax, float &ay)
+{
+    int r = 0;
+    for (; r + 8 <= len; r += 8) {
+        float2 h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = col[(int64_t)(r + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float vq = v[r + u];
+            ax += h[u].x * vq;
+            ay += h[u].y * vq;
+        }
+    }
+    for (; r < len; ++r) {
+        const float2 h = col[(int64_t)r * stride];
+        ax += h.x * v[r];
+        ay += h.y * v[r];
+    }
+}
+
 // y = H v for a symmetric H (d x d, d even, 8-byte aligned), as column sums:
 // y_r = sum_q H[q][r] v[q] in ascending q per row slice, slices added in
-// order (deterministic).  Every thread of the block calls it; ends with a
-// barrier.
+// order (deterministic).  part holds 2 BLOCK partial sums.  Every thread of
+// the block calls it; ends with a barrier.
 template <int BLOCK>
 __device__ void sym_matvec(const float *__restrict__ H, int d, const float *v, float *y,
                            float2 *part)
@@ -104,33 +137,75 @@ __device__ void sym_matvec(const float *__restrict__ H, int d, const float *v, f
     const int t = (int)threadIdx.x;
     const SymSplit sp(d, BLOCK);
     const float2 *H2 = reinterpret_cast<const float2 *>(H);
-    for (int base = 0; base < sp.cp; base += BLOCK) {
-        const int pairs = sp.cp - base < BLOCK ? sp.cp - base : BLOCK;
-        const int nq = base == 0 ? sp.nq : 1;
-        if (t < pairs * nq) {
-            const int pr = base + t % pairs, sl = t / pairs;
-            const int q0 = (int)((int64_t)d * sl / nq), q1 = (int)((int64_t)d * (sl + 1) / nq);
-            float ax = 0.f, ay = 0.f;
-#pragma unroll 16
-            for (int q = q0; q < q1; ++q) {
-                const float2 h = H2[(int64_t)q * sp.cp + pr];
-                const float vq = v[q];
-                ax += h.x * vq;
-                ay += h.y * vq;
-            }
-            part[t] = make_float2(ax, ay);
+    int pa, qa0, qa1, pb, qb0, qb1;
+    sp.item(t, d, pa, qa0, qa1);
+    sp.item(t + BLOCK, d, pb, qb0, qb1);
+    const int La = qa1 - qa0, Lb = qb1 - qb0;
+    const int64_t st = sp.cp;
+    const float2 *ca = H2 + (int64_t)qa0 * st + pa, *cb = H2 + (int64_t)qb0 * st + pb;
+    float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
+    // both streams side by side while both have rows, 8 loads each in flight
+    const int L2 = La < Lb ? La : Lb;
+    int r = 0;
+    for (; r + 8 <= L2; r += 8) {
+        float2 ha[8], hb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            ha[u] = ca[(int64_t)(r + u) * st];
+            hb[u] = cb[(int64_t)(r + u) * st];
         }
-        __syncthreads();
-        for (int r = t; r < pairs; r += BLOCK) {
-            float2 a = part[r];
-            for (int j = 1; j < nq; ++j) {
-                a.x += part[j * pairs + r].x;
-                a.y += part[j * pairs + r].y;
-            }
-            y[2 * (base + r)] = a.x;
-            y[2 * (base + r) + 1] = a.y;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float va = v[qa0 + r + u], vb = v[qb0 + r + u];
+            ax += ha[u].x * va;
+            ay += ha[u].y * va;
+            bx += hb[u].x * vb;
+            by += hb[u].y * vb;
         }
-        __syncthreads();
+    }
+    col_dot(ca + (int64_t)r * st, st, v + qa0 + r, La - r, ax, ay);
+    col_dot(cb + (int64_t)r * st, st, v + qb0 + r, Lb - r, bx, by);
+    if (t < sp.items) part[t] = make_float2(ax, ay);
+    if (t + BLOCK < sp.items) part[t + BLOCK] = make_float2(bx, by);
+    __syncthreads();
+    for (int k = t; k < sp.cp; k += BLOCK) {
+        float2 acc = part[k];
+        for (int j = 1; j < sp.nq; ++j) {
+            acc.x += part[j * sp.cp + k].x;
+            acc.y += part[j * sp.cp + k].y;
+        }
+        y[2 * k] = acc.x;
+        y[2 * k + 1] = acc.y;
+    }
+    __syncthreads();
+}
+
+// Rank-2 update of rows [q0, q0 + len) of one column pair: batches of 8
+// loads, the updates, then the 8 stores.
+__device__ __forceinline__ void col_rank2(float2 *__restrict__ col, int64_t stride, const float *s,
+                                          const float *w, int len, float s0, float s1, float w0,
+                                          float w1, float ib, float a2)
+{
+    int r = 0;
+    for (; r + 8 <= len; r += 8) {
+        float2 h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = col[(int64_t)(r + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float sq_ = s[r + u], wq = w[r + u];
+            h[u].x = h[u].x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
+            h[u].y = h[u].y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) col[(int64_t)(r + u) * stride] = h[u];
+    }
+    for (; r < len; ++r) {
+        const float sq_ = s[r], wq = w[r];
+        float2 h = col[(int64_t)r * stride];
+        h.x = h.x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
+        h.y = h.y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
+        col[(int64_t)r * stride] = h;
     }
 }
 
@@ -142,23 +217,14 @@ __device__ void sym_rank2(float *__restrict__ H, int d, const float *s, const fl
     const int t = (int)threadIdx.x;
     const SymSplit sp(d, BLOCK);
     float2 *H2 = reinterpret_cast<float2 *>(H);
-    for (int base = 0; base < sp.cp; base += BLOCK) {
-        const int pairs = sp.cp - base < BLOCK ? sp.cp - base : BLOCK;
-        const int nq = base == 0 ? sp.nq : 1;
-        if (t < pairs * nq) {
-            const int pr = base + t % pairs, sl = t / pairs;
-            const int q0 = (int)((int64_t)d * sl / nq), q1 = (int)((int64_t)d * (sl + 1) / nq);
-            const float s0 = s[2 * pr], s1 = s[2 * pr + 1], w0 = w[2 * pr], w1 = w[2 * pr + 1];
-#pragma unroll 8
-            for (int q = q0; q < q1; ++q) {
-                const float sq_ = s[q], wq = w[q];
-                float2 h = H2[(int64_t)q * sp.cp + pr];
-                h.x = h.x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
-                h.y = h.y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
-                H2[(int64_t)q * sp.cp + pr] = h;
-            }
-        }
-    }
+    int pa, qa0, qa1, pb, qb0, qb1;
+    sp.item(t, d, pa, qa0, qa1);
+    sp.item(t + BLOCK, d, pb, qb0, qb1);
+    const int64_t st = sp.cp;
+    col_rank2(H2 + (int64_t)qa0 * st + pa, st, s + qa0, w + qa0, qa1 - qa0, s[2 * pa],
+              s[2 * pa + 1], w[2 * pa], w[2 * pa + 1], ib, a2);
+    col_rank2(H2 + (int64_t)qb0 * st + pb, st, s + qb0, w + qb0, qb1 - qb0, s[2 * pb],
+              s[2 * pb + 1], w[2 * pb], w[2 * pb + 1], ib, a2);
     __syncthreads();
 }
 struct NoShared {
