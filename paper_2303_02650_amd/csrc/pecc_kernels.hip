@@ -225,44 +225,88 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
         return;
     }
     const bool staged = len <= kColLds;
-    // positions: float4 loads where the instance start is 16-byte aligned
-    if ((reinterpret_cast<uintptr_t>(xy + 2 * (int64_t)off) & 15) == 0) {
-        const float4 *src = reinterpret_cast<const float4 *>(xy + 2 * (int64_t)off);
-        float4 *dst = reinterpret_cast<float4 *>(pos);
-        typedef float v4f __attribute__((ext_vector_type(4)));
-        for (int k = threadIdx.x; k < n / 2; k += kSweepBlock) {
-            const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(&src[k]));
-            dst[k] = make_float4(t.x, t.y, t.z, t.w);
+    // One batch of streaming loads per thread -- positions as float4 where
+    // the instance start is 16-byte aligned, the list segment as int4 -- all
+    // issued before the first is used, so the workgroup waits for memory
+    // once; then the LDS writes (list entries as 16-bit local indices).
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    constexpr int kPV = (kMaxN / 2 + kSweepBlock - 1) / kSweepBlock;   // float4 per thread
+    constexpr int kCV = (kColLds / 4 + kSweepBlock - 1) / kSweepBlock; // int4 per thread
+    const bool pos_al = (reinterpret_cast<uintptr_t>(xy + 2 * (int64_t)off) & 15) == 0;
+    const int npv = pos_al ? n / 2 : 0;
+    const v4f *psrc = reinterpret_cast<const v4f *>(xy + 2 * (int64_t)off);
+    const int mis = (int)((reinterpret_cast<uintptr_t>(col + r0) & 15) >> 2);
+    const int head = staged ? min(len, (4 - mis) & 3) : 0;
+    const int nv = staged ? (len - head) >> 2 : 0;
+    const v4i *csrc = reinterpret_cast<const v4i *>(col + r0 + head);
+    // unconditional loads (indices clamped into range; the extra lanes'
+    // values are dropped below), so nothing waits between them
+    v4f pv[kPV];
+    v4i cv[kCV];
+    if (npv > 0) {
+#pragma unroll
+        for (int u = 0; u < kPV; ++u) {
+            const int k = threadIdx.x + u * kSweepBlock;
+            pv[u] = __builtin_nontemporal_load(psrc + (k < npv ? k : 0));
         }
-        if ((n & 1) && threadIdx.x == 0) pos[n - 1] = reinterpret_cast<const float2 *>(xy)[off + n - 1];
-    } else {
+    }
+    if (nv > 0) {
+#pragma unroll
+        for (int u = 0; u < kCV; ++u) {
+            const int v = threadIdx.x + u * kSweepBlock;
+            cv[u] = __builtin_nontemporal_load(csrc + (v < nv ? v : 0));
+        }
+    }
+    // row bounds of this thread's circles tid + 256 c (indices clamped to n)
+    constexpr int kRC = kMaxN / kSweepBlock;
+    int rw[kRC + 1];
+#pragma unroll
+    for (int c = 0; c <= kRC; ++c) {
+        const int i = threadIdx.x + c * kSweepBlock;
+        rw[c] = row[off + (i < n ? i : n)];
+    }
+    int rw1[kRC];
+#pragma unroll
+    for (int c = 0; c < kRC; ++c) {
+        const int i = threadIdx.x + c * kSweepBlock + 1;
+        rw1[c] = row[off + (i < n ? i : n)];
+    }
+    auto put = [&](int k, int v) {
+        const int jj = v - off;
+        col_s[k] = (unsigned)jj < (unsigned)n ? (uint16_t)jj : (uint16_t)0xFFFF;
+    };
+    if (!pos_al) {
         stage_positions<kSweepBlock>(xy, off, n, pos);
+    } else if ((n & 1) && threadIdx.x == 0) {
+        pos[n - 1] = reinterpret_cast<const float2 *>(xy)[off + n - 1];
     }
     if (staged) {
-        auto put = [&](int k, int v) {
-            const int jj = v - off;
-            col_s[k] = (unsigned)jj < (unsigned)n ? (uint16_t)jj : (uint16_t)0xFFFF;
-        };
-        const int mis = (int)((reinterpret_cast<uintptr_t>(col + r0) & 15) >> 2);
-        const int head = min(len, (4 - mis) & 3);
-        const int nv = (len - head) >> 2;
         if ((int)threadIdx.x < head) put(threadIdx.x, col[r0 + threadIdx.x]);
-        typedef int v4i __attribute__((ext_vector_type(4)));
-        const v4i *src4 = reinterpret_cast<const v4i *>(col + r0 + head);
-#pragma unroll 2
-        for (int v = threadIdx.x; v < nv; v += kSweepBlock) {
-            const v4i t = __builtin_nontemporal_load(&src4[v]);
-            const int k = head + 4 * v;
-            put(k, t.x); put(k + 1, t.y); put(k + 2, t.z); put(k + 3, t.w);
-        }
         for (int k = head + 4 * nv + threadIdx.x; k < len; k += kSweepBlock) put(k, col[r0 + k]);
+    }
+#pragma unroll
+    for (int u = 0; u < kPV; ++u) {
+        const int k = threadIdx.x + u * kSweepBlock;
+        if (k < npv) reinterpret_cast<float4 *>(pos)[k] = make_float4(pv[u].x, pv[u].y, pv[u].z, pv[u].w);
+    }
+#pragma unroll
+    for (int u = 0; u < kCV; ++u) {
+        const int v = threadIdx.x + u * kSweepBlock;
+        if (v < nv) {
+            const int k = head + 4 * v;
+            put(k, cv[u].x); put(k + 1, cv[u].y); put(k + 2, cv[u].z); put(k + 3, cv[u].w);
+        }
     }
     __syncthreads();
     const float Rb = R[b];
     const float two_r = 2.0f * rad, four_r2 = two_r * two_r;
     float e = 0.0f;
     const bool g_al = (reinterpret_cast<uintptr_t>(grad) & 7) == 0;
-    for (int i0 = threadIdx.x; i0 < n; i0 += 2 * kSweepBlock) {
+#pragma unroll
+    for (int pass = 0; pass < kRC / 2; ++pass) {
+      const int i0 = threadIdx.x + 2 * kSweepBlock * pass;
+      if (i0 >= n) break;
       // two circles per pass (i0 and i0 + kSweepBlock): their list and
       // position reads overlap; each keeps its own order of terms
       float gxA[2], gyA[2], eiA[2];
@@ -273,7 +317,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
           gxA[h] = gyA[h] = eiA[h] = 0.f;
           aA[h] = 0; zA[h] = 0;
           if (i < n) {
-              int a = row[off + i] - r0, z = row[off + i + 1] - r0;
+              int a = rw[2 * pass + h] - r0, z = rw1[2 * pass + h] - r0;
               aA[h] = a < 0 ? 0 : a;
               zA[h] = z > len ? len : z;
           }
