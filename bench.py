@@ -37,7 +37,7 @@ COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
 # measured on the 1 GiB copy): profiles/energy_grad_kernel_traffic_65536x1000.md.
 # Valid for the kernel as profiled; None for other batch sizes.
-SWEEP_TRAFFIC_BYTES_65536 = None
+SWEEP_TRAFFIC_BYTES_65536 = 2.5748e9
 # HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
 # (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
 DESCENT_TRAFFIC_BYTES_256 = 4.7e6

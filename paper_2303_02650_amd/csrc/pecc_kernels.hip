@@ -387,9 +387,10 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
 // FP64 verify: every pair of the instance once.  Circle i is paired with
 // the next floor((n-1)/2) circles cyclically (and, for even n, with i+n/2
 // when i < n/2), which visits each unordered pair exactly once and gives
-// every thread the same amount of work.
+// every thread the same amount of work.  512 threads per instance, and the
+// partner positions read four at a time, so that LDS latency overlaps.
 // ---------------------------------------------------------------------------
-constexpr int kVerifyBlock = 256;
+constexpr int kVerifyBlock = 512;
 
 __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ R,
@@ -420,17 +421,33 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     for (int i = threadIdx.x; i < n; i += kVerifyBlock) {
         const double xi = pos[i].x, yi = pos[i].y;
         const int extra = (even && i < n / 2) ? 1 : 0;
-        for (int t = 1; t <= half + extra; ++t) {
-            int j = i + t;
-            if (j >= n) j -= n;
-            const double dx = __dsub_rn(xi, (double)pos[j].x);
-            const double dy = __dsub_rn(yi, (double)pos[j].y);
+        const int cnt = half + extra;
+        auto pair = [&](float2 pj) {
+            const double dx = __dsub_rn(xi, (double)pj.x);
+            const double dy = __dsub_rn(yi, (double)pj.y);
             const double l2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
             if (l2 < 4.0) {
                 const double d = __dsub_rn(2.0, sqrt(l2));
                 sp = __dadd_rn(sp, __dmul_rn(d, d));
                 mp = fmax(mp, d);
             }
+        };
+        int t = 1;
+        for (; t + 3 <= cnt; t += 4) {
+            float2 pj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int j = i + t + u;
+                if (j >= n) j -= n;
+                pj[u] = pos[j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pair(pj[u]);
+        }
+        for (; t <= cnt; ++t) {
+            int j = i + t;
+            if (j >= n) j -= n;
+            pair(pos[j]);
         }
         const double rho = sqrt(__dadd_rn(__dmul_rn(xi, xi), __dmul_rn(yi, yi)));
         const double d0 = __dsub_rn(__dadd_rn(rho, 1.0), Rb);
