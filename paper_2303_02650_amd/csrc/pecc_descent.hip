@@ -314,7 +314,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         const Grid grid = make_grid(R, A.h_req);
 
         // ---- batch descent: batch of every circle, batch sizes --------------
-        int batc[kCPT] = {};            // batch of each circle of this thread
+        // batch of circle tid + c * kDB (read from LDS where needed, so no
+        // registers stay live for it; stale for circles beyond n, which no
+        // use reads without act[c])
+        auto batc_of = [&](int c) -> int {
+            if constexpr (SEQ) return sq.bat[(int)threadIdx.x + c * kDB];
+            else return 0;
+        };
         bool visits = false;            // more than one non-empty batch
         int first_b = 0;                // first non-empty batch
         if constexpr (SEQ) {
@@ -332,7 +338,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     if (v < 0 || v >= A.nbat) {
                         bad = 1;
                     } else {
-                        batc[c] = v;
                         sq.bat[i] = (uint8_t)v;
                         atomicAdd(&sq.cnt[v], 1);
                     }
@@ -367,7 +372,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const int i = tid + c * kDB;
                 if (i < n) {
                     int r = 0;
-                    for (int j = 0; j < i; ++j) r += sq.bat[j] == batc[c] ? 1 : 0;
+                    const int bi = sq.bat[i];
+                    for (int j = 0; j < i; ++j) r += sq.bat[j] == bi ? 1 : 0;
                     sq.memb[i] = (uint16_t)r;
                 }
             }
@@ -532,7 +538,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = t0 + c * kDB;
-                    if (act[c] && batc[c] == cb) {
+                    if (act[c] && batc_of(c) == cb) {
                         const int m = sq.memb[i];
                         sq.vb[0][2 * m] = u[c].x;
                         sq.vb[0][2 * m + 1] = u[c].y;
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = t0 + c * kDB;
-                    if (act[c] && batc[c] == cb) {
+                    if (act[c] && batc_of(c) == cb) {
                         const int m = sq.memb[i];
                         p[c] = make_float2(-sq.vb[2][2 * m], -sq.vb[2][2 * m + 1]);
                     } else {
@@ -633,7 +639,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             const bool want64 = fp64 || (SEQ && req == kReqTotal);
             bool inb[kCPT];
 #pragma unroll
-            for (int c = 0; c < kCPT; ++c) inb[c] = !masked || batc[c] == cb;
+            for (int c = 0; c < kCPT; ++c) inb[c] = !masked || batc_of(c) == cb;
             // container radius of this evaluation (a variable only when adjusting)
             const float Rt = ADJ ? (req == kReqTrial ? fmaf(alpha, pR, Rz) : Rz) : R;
 #pragma unroll
@@ -1100,7 +1106,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             px -= csj * S[j][c].x + cyj * Y[j][c].x;
                             py -= csj * S[j][c].y + cyj * Y[j][c].y;
                         }
-                        p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(px, py)
+                        p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(px, py)
                                                                   : make_float2(0.f, 0.f);
                     }
                     if constexpr (ADJ) {
@@ -1118,7 +1124,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if constexpr (DENSE) dense_reset();
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c)
-                    p[c] = (!SEQ || !visits || batc[c] == cb) ? make_float2(-g[c].x, -g[c].y)
+                    p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(-g[c].x, -g[c].y)
                                                               : make_float2(0.f, 0.f);
                 if constexpr (ADJ) pR = -gR;
                 gp = -gg;
