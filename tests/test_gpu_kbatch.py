@@ -30,7 +30,7 @@ def ragged():
     """Instances of 0, 1, 3, 17 circles, a C3 restart and a C2 start."""
     rng = synth.rng_for(77)
     parts, radii = [], []
-    for n in (0, 1, 3, 17):
+    for n in (0, 1, 3, 17, 1024):
         R = max(2.0, float(np.sqrt(max(n, 1) / 0.7)))
         u = rng.random((n, 2))
         r = (R - 1.0) * np.sqrt(u[:, 0])
@@ -282,3 +282,46 @@ def test_dense_with_anm_follows_oracle_early(P):
                                              anm=True, lcut=4.0, dense=True)
         assert np.abs(xg - x64).max() < 5e-5 * outer * max(1.0, np.abs(x64).max())
         assert res["rebuilds"][0] == 1 + r64["anm_changes"], outer
+
+
+def test_more_batches_than_circles_and_empty_instances(P):
+    """k > n leaves batches empty (skipped); an empty instance is FEASIBLE at
+    once; the first outer iterations still follow the oracle."""
+    rng = synth.rng_for(12)
+    parts = [np.zeros((0, 2), np.float32), synth.disk_uniform(3, 2.2, rng).astype(np.float32),
+             synth.disk_uniform(6, 2.6, rng).astype(np.float32)]
+    inst = synth.pack(parts, [2.0, 2.2, 2.6])
+    k = 5
+    bo = host_partition(inst, "sector", k)
+    params = P.DescentParams(max_iter=2, g_tol=0.0, ftol=0.0)
+    xg, res = run(P, inst, bo, k, params)
+    assert P.STATUS[res["status"][0]] == "FEASIBLE"
+    for b in (1, 2):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_seq_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                             bo[o0:o1], k, oracle.DescentParams(g_tol=0.0),
+                                             max_outer=2)
+        assert res["iters"][b] == r64["outer"]
+        assert np.abs(xg[o0:o1] - x64).max() < 1e-4 * max(1.0, np.abs(x64).max())
+
+
+def test_anm_crowded_lists_overflow(P):
+    """35 circles inside a disk of radius 0.6 have more than 32 neighbors
+    within l_cut = 4: the sweep falls back to the cell grid, the descent stays
+    deterministic and its energy does not grow."""
+    rng = synth.rng_for(8)
+    core = synth.disk_uniform(35, 1.6, rng)
+    rest = synth.disk_uniform(25, 8.0, rng)
+    inst = synth.pack([np.concatenate([core, rest]).astype(np.float32)], [8.0])
+    bo = host_partition(inst, "sector", 3)
+    E0 = oracle.energy(inst.instance(0).astype(np.float64), 8.0)
+    prev = None
+    for t in (1, 4, 16):
+        params = P.DescentParams(max_iter=t, g_tol=0.0, ftol=0.0, cutoff=4.0)
+        xa, ra = run(P, inst, bo, 3, params, anm=True)
+        xb, rb = run(P, inst, bo, 3, params, anm=True)
+        assert np.array_equal(xa, xb)
+        assert oracle.energy(xa.astype(np.float64), 8.0) < E0
+        E = float(ra["E32"][0])          # the descent's own objective
+        assert prev is None or E <= prev * (1 + 1e-6)
+        prev = E
