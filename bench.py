@@ -41,6 +41,12 @@ SWEEP_TRAFFIC_BYTES_65536 = 2.5748e9
 # HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
 # (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
 DESCENT_TRAFFIC_BYTES_256 = 4.7e6
+# Instruction counters of the same launch (SQ_INSTS_VALU per wave per
+# evaluation, SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES):
+# profiles/lbfgs_descend_kernel_sq_counters_256x1000.md.  Valid for the
+# kernel as profiled.
+DESCENT_VALU_PER_WAVE_EVAL_256 = 1922
+DESCENT_VALU_ACTIVE_SHARE_256 = 0.371
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
@@ -376,7 +382,12 @@ def main():
     roof = {"kernel": "lbfgs_descend_kernel", "bound": "alu", "achieved": achieved_tf,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP32_PEAK_TFLOPS,
             "traffic": DESCENT_TRAFFIC_BYTES_256 if (a.batch == 256 and a.max_iter == 5000) else None,
-            "per_launch_flops": flops, "avg_launch_ms": t_desc * 1e3}
+            "per_launch_flops": flops, "avg_launch_ms": t_desc * 1e3,
+            # the running kernel is bound by vector-instruction issue, most
+            # of which are not algorithmic flops (counter profile)
+            "valu_instructions_per_wave_eval": DESCENT_VALU_PER_WAVE_EVAL_256 if a.batch == 256 else None,
+            "valu_active_share_of_wave_time": DESCENT_VALU_ACTIVE_SHARE_256 if a.batch == 256 else None,
+            "busy_cu_share": float(res["iters"].mean() / max(1, res["iters"].max()))}
 
     line = {
         "metric": "L-BFGS descents/sec at n=1000 (batched FP32, persistent launch), to E<1e-20 or convergence",
