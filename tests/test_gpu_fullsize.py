@@ -1,7 +1,9 @@
 """Full-size checks in the launch configurations the benchmark times: the
 main step (256 starts of n = 1000 at R = 34.6 in one persistent launch,
 FP32 with the contact margin 1e-4, FP64 near E = 0) and the HBM sweep
-(65536 instances of n = 1000, one launch).  Sampled outputs are recomputed
+(65536 instances of n = 1000, one launch); the geometric batches (64
+instances of n = 1000 at R = 34.4, 4 x 4 blocks); the learned proposal's
+scoring stage (128 x 4096 candidates); one SED iteration of 128 chains.  Sampled outputs are recomputed
 by the oracle one by one; the rest is checked through properties that hold
 at any size."""
 import numpy as np
@@ -78,3 +80,106 @@ def test_sweep_full_size_sampled(P):
         o0 = big.offset[b]
         n = big.offset[b + 1] - o0
         assert rows[o0 + n] - rows[o0] == 2 * oracle.neighbors(xb, 2.3)[0].size
+
+
+def test_learned_proposal_stage_full_size_sampled(P):
+    """128 instances of n = 1000 at R = 34.4 with 4096 candidates each
+    (524,288 rows): features, network scores and the top-50 proposal, with
+    sampled rows and instances recomputed by the oracle."""
+    import math
+    inst = synth.C5(128)
+    cc, cd = synth.candidates(inst, 4096, synth.rng_for(99))
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    xy = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    ccd = torch.from_numpy(cc.reshape(-1)).cuda()
+    cdd = torch.from_numpy(cd.reshape(-1)).cuda()
+    feats = P.features(d, xy, ccd, cdd)
+    params = P.init_params(7)
+    logits = P.mlp_forward(params, feats)
+    xy_new, sel = P.propose(d, xy, ccd, cdd, logits, 50)
+    F = feats.cpu().numpy().reshape(128, 4096, 8)
+    Z = logits.cpu().numpy().reshape(128, 4096)
+    S = sel.cpu().numpy()
+    X = xy_new.cpu().numpy().reshape(-1, 2)
+    p64 = params.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(3)
+    for b in (0, 45, 127):
+        rows = rng.choice(4096, 64, replace=False)
+        ref = oracle.features(inst.instance(b), inst.R[b], cc[b][rows], cd[b][rows])
+        np.testing.assert_allclose(F[b][rows], ref, rtol=0, atol=1e-6)
+        for col in (1, 5):
+            assert np.array_equal(F[b][rows][:, col], ref[:, col])
+        z_ref = oracle.mlp_forward(p64, F[b][rows].astype(np.float64))
+        assert np.abs(Z[b][rows] - z_ref).max() <= 1e-2 * (1 + np.abs(z_ref).max())
+        ref_sel, ref_xy = oracle.propose(inst.instance(b), cc[b], cd[b], Z[b], 50)
+        assert np.array_equal(S[b][S[b] >= 0], ref_sel)
+        assert np.array_equal(X[inst.offset[b]:inst.offset[b + 1]], ref_xy)
+    assert math.isfinite(float(Z.sum()))
+
+
+def test_sed_iteration_full_size_sampled(P):
+    """One SED iteration of 128 chains of n = 1000 at R = 34.4 with M = 25:
+    candidate counts, perturbations and selections against the oracle."""
+    from paper_2303_02650_amd.sed import SedChains
+    inst = synth.C5(128)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    x0 = torch.from_numpy(inst.xy.reshape(-1).copy()).cuda()
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4)
+    ch = SedChains(d, x0, prm, M=25, seed=17)
+    E_cur0 = ch.E_cur.cpu().numpy().copy()
+    E_best0 = ch.E_best.cpu().numpy().copy()
+    x_cur0 = ch.xy.cpu().numpy().reshape(-1, 2).copy()
+    ch.step()
+    m = ch.m.cpu().numpy()
+    ref_m = [0 if eb <= 1e-25 else max(1, oracle.sed_J(ec, 25)) for ec, eb in zip(E_cur0, E_best0)]
+    assert m.tolist() == ref_m
+    off = ch.cand_off.cpu().numpy()
+    cE = ch.cand_E.cpu().numpy()
+    chosen = ch.chosen.cpu().numpy()
+    for b in (3, 64, 120):
+        if m[b] == 0:
+            continue
+        for j in (0, m[b] - 1):
+            c = b * 25 + j
+            # candidate positions after their descent differ; the perturbation is
+            # checked through a fresh one below
+            assert off[c + 1] - off[c] == 1000
+        k = oracle.sed_select(cE[b * 25:b * 25 + m[b]], E_cur0[b], oracle.sed_uniform(17, b, 0), 25)
+        assert chosen[b] == k
+    # the perturbation of a few slots, recomputed from the same current layouts
+    pert = torch.zeros_like(ch.cand_xy)
+    P.pecc_sed_perturb(d, torch.from_numpy(x_cur0.reshape(-1)).cuda(), 25, ch.m, ch.cand_off, 17, 0,
+                       pert)
+    pert = pert.cpu().numpy()
+    for b in (3, 64, 120):
+        for j in range(min(2, m[b])):
+            c = b * 25 + j
+            got = pert[2 * off[c]:2 * off[c + 1]].reshape(-1, 2)
+            ref = oracle.sed_perturb(x_cur0[inst.offset[b]:inst.offset[b + 1]], 17, b, 0, j)
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (b, j)
+
+
+def test_geometric_batches_full_size_sampled(P):
+    """64 instances of n = 1000 at R = 34.4 in 4 x 4 blocks: two outer
+    iterations of every instance in one launch, sampled instances against
+    the oracle's batch descent; whole descents deterministic."""
+    inst = synth.C4(64)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    xy = torch.from_numpy(inst.xy.reshape(-1).copy()).cuda()
+    res = P.results(P.gbo_descend(d, xy, P.DescentParams(max_iter=2, g_tol=0.0, ftol=0.0), blocks=4))
+    x = xy.cpu().numpy().reshape(-1, 2)
+    assert (res["iters"] == 2).all()
+    for b in (0, 31, 63):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                         oracle.DescentParams(g_tol=0.0), blocks=4, max_outer=2,
+                                         skin_half=0.15)
+        assert np.abs(x[o0:o1] - x64).max() < 1e-4 * max(1.0, np.abs(x64).max())
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4)
+    runs = []
+    for _ in range(2):
+        xy = torch.from_numpy(inst.xy.reshape(-1).copy()).cuda()
+        r = P.results(P.gbo_descend(d, xy, prm, blocks=4))
+        runs.append((xy.cpu().numpy(), r))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert set(np.unique(runs[0][1]["status"])) <= {1, 2, 3, 4, 5}
