@@ -142,10 +142,11 @@ def kbatch_study(P, a, dev, stream):
             torch.cuda.synchronize()
             r = P.results(outd)
             ms = e0.elapsed_time(e1)
-            # matrix bytes: per visit two reads (H g, H y) and one read +
-            # write (Eq. 11), counting every visit as updating its matrix
+            # matrix bytes: per visit one read and one write (the pass that
+            # forms H g and applies the pending update of Eq. 11), counting
+            # every visit as updating its matrix
             vis = float(r["iters"].astype(np.float64).sum()) * k
-            mbytes = vis * 4 * 4 * (2 * 1000 / k) ** 2
+            mbytes = vis * 2 * 4 * (2 * 1000 / k) ** 2
             dense[f"sector_k{k}"] = {
                 "kernel_ms": ms, "descents_per_s": dd.B / (ms / 1e3),
                 "matrix_bytes_per_instance": 4 * k * (2 * mb) ** 2,

@@ -294,7 +294,10 @@ namespace {
 // circles: sum_p d_p^2 <= (2 max_batch) sum_p d_p <= 4 max_batch max_n
 int64_t dense_stride(const pecc_instances *inst, int32_t max_batch)
 {
-    return 4 * (int64_t)max_batch * (int64_t)(inst->max_n > 0 ? inst->max_n : 1);
+    // the matrices (sum of (2|B_p|)^2 <= 4 max_batch n) and four vectors of
+    // 2|B_p| floats per batch (8 n)
+    const int64_t n = inst->max_n > 0 ? inst->max_n : 1;
+    return 4 * (int64_t)max_batch * n + 8 * n;
 }
 }  // namespace
 

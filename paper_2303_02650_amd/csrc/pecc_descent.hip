@@ -66,17 +66,24 @@ struct SeqShared {
     int cnt[kMaxSeqBatches];
 };
 // Dense batch descent: batch ids and sizes, every circle's index inside its
-// batch, each batch's matrix offset, three vectors of a batch's
-// coordinates, per-wave partial sums.
+// batch, each batch's matrix and vector offsets in the workspace, four
+// vectors of a batch's coordinates staged for a matrix pass, per-wave
+// partial sums, and the pass's per-item partial sums (two products).
 struct DenseShared {
     uint8_t bat[kMaxN];
     int cnt[kMaxSeqBatches];
     uint16_t memb[kMaxN];
     int hoff[kMaxSeqBatches + 1];
-    float vb[3][2 * kMaxN];
-    float wpart[kDB / kWave];
-    float2 part[2 * kDB];
+    int voff[kMaxSeqBatches + 1];
+    float vb[4][2 * kMaxN];
+    float wpart[4][kDB / kWave];
+    float4 part[2 * kDB];
 };
+
+// Per-batch state of the dense descent (bits of a lane-indexed word): the
+// stored matrix S still stands for I (never written), a known pending
+// update K, a newest curvature pair Q, which of the two s slots holds K's s.
+enum : int { kDnIdent = 1, kDnK = 2, kDnQ = 4, kDnSlot = 8 };
 
 // Work split of a pass over a symmetric d x d matrix (d even, d <= 2048)
 // stored row-major: an item is a column pair pr (two consecutive columns,
@@ -102,117 +109,72 @@ struct SymSplit {
     }
 };
 
-// Column-pair dot product of rows [q, q + len) of one item: batches of 8
-// independent loads, then the FMAs (rows ascending).
-__device__ __forceinline__ void col_dot(const float2 *__restrict__ col, int64_t stride,
-                                        const float *v, int len, float &ax, float &ay)
+// One element pair (row r, columns 2pc and 2pc + 1) of a matrix pass:
+// h is S's pair (I's when nothing is read); the two products take S's
+// values, and with STORE h becomes S + U for the symmetric rank-2 update
+// U = -(w s' + s w') ib + a2 s s' (s0, s1, w0, w1: s and w at the two
+// columns).  v[0] = g, v[1] = y, v[2] = s, v[3] = w.
+template <bool STORE>
+__device__ __forceinline__ void pass_elem(float2 &h, int r, const float *const (&v)[4], float s0,
+                                          float s1, float w0, float w1, float ib, float a2,
+                                          float4 &acc)
 {
-    int r = 0;
-    for (; r + 8 <= len; r += 8) {
-        float2 h[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) h[u] = col[(int64_t)(r + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float vq = v[r + u];
-            ax += h[u].x * vq;
-            ay += h[u].y * vq;
-        }
-    }
-    for (; r < len; ++r) {
-        const float2 h = col[(int64_t)r * stride];
-        ax += h.x * v[r];
-        ay += h.y * v[r];
-    }
-}
-
-// y = H v for a symmetric H (d x d, d even, 8-byte aligned), as column sums:
-// y_r = sum_q H[q][r] v[q] in ascending q per row slice, slices added in
-// order (deterministic).  part holds 2 BLOCK partial sums.  Every thread of
-// the block calls it; ends with a barrier.
-template <int BLOCK>
-__device__ void sym_matvec(const float *__restrict__ H, int d, const float *v, float *y,
-                           float2 *part)
-{
-    const int t = (int)threadIdx.x;
-    const SymSplit sp(d, BLOCK);
-    const float2 *H2 = reinterpret_cast<const float2 *>(H);
-    int pa, qa0, qa1, pb, qb0, qb1;
-    sp.item(t, d, pa, qa0, qa1);
-    sp.item(t + BLOCK, d, pb, qb0, qb1);
-    const int La = qa1 - qa0, Lb = qb1 - qb0;
-    const int64_t st = sp.cp;
-    const float2 *ca = H2 + (int64_t)qa0 * st + pa, *cb = H2 + (int64_t)qb0 * st + pb;
-    float ax = 0.f, ay = 0.f, bx = 0.f, by = 0.f;
-    // both streams side by side while both have rows, 8 loads each in flight
-    const int L2 = La < Lb ? La : Lb;
-    int r = 0;
-    for (; r + 8 <= L2; r += 8) {
-        float2 ha[8], hb[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            ha[u] = ca[(int64_t)(r + u) * st];
-            hb[u] = cb[(int64_t)(r + u) * st];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float va = v[qa0 + r + u], vb = v[qb0 + r + u];
-            ax += ha[u].x * va;
-            ay += ha[u].y * va;
-            bx += hb[u].x * vb;
-            by += hb[u].y * vb;
-        }
-    }
-    col_dot(ca + (int64_t)r * st, st, v + qa0 + r, La - r, ax, ay);
-    col_dot(cb + (int64_t)r * st, st, v + qb0 + r, Lb - r, bx, by);
-    if (t < sp.items) part[t] = make_float2(ax, ay);
-    if (t + BLOCK < sp.items) part[t + BLOCK] = make_float2(bx, by);
-    __syncthreads();
-    for (int k = t; k < sp.cp; k += BLOCK) {
-        float2 acc = part[k];
-        for (int j = 1; j < sp.nq; ++j) {
-            acc.x += part[j * sp.cp + k].x;
-            acc.y += part[j * sp.cp + k].y;
-        }
-        y[2 * k] = acc.x;
-        y[2 * k + 1] = acc.y;
-    }
-    __syncthreads();
-}
-
-// Rank-2 update of rows [q0, q0 + len) of one column pair: batches of 8
-// loads, the updates, then the 8 stores.
-__device__ __forceinline__ void col_rank2(float2 *__restrict__ col, int64_t stride, const float *s,
-                                          const float *w, int len, float s0, float s1, float w0,
-                                          float w1, float ib, float a2)
-{
-    int r = 0;
-    for (; r + 8 <= len; r += 8) {
-        float2 h[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) h[u] = col[(int64_t)(r + u) * stride];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float sq_ = s[r + u], wq = w[r + u];
-            h[u].x = h[u].x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
-            h[u].y = h[u].y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) col[(int64_t)(r + u) * stride] = h[u];
-    }
-    for (; r < len; ++r) {
-        const float sq_ = s[r], wq = w[r];
-        float2 h = col[(int64_t)r * stride];
+    const float gq = v[0][r], yq = v[1][r];
+    acc.x += h.x * gq;
+    acc.y += h.y * gq;
+    acc.z += h.x * yq;
+    acc.w += h.y * yq;
+    if constexpr (STORE) {
+        const float sq_ = v[2][r], wq = v[3][r];
         h.x = h.x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
         h.y = h.y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
-        col[(int64_t)r * stride] = h;
     }
 }
 
-// H += -(w s' + s w') ib + a2 s s' (symmetric rank-2 update, same split).
-template <int BLOCK>
-__device__ void sym_rank2(float *__restrict__ H, int d, const float *s, const float *w, float ib,
-                          float a2)
+template <bool LOAD>
+__device__ __forceinline__ float2 pass_load(const float2 *col, int64_t st, int rr, int r, int pc)
+{
+    if constexpr (LOAD) return col[(int64_t)rr * st];
+    else return make_float2(r == 2 * pc ? 1.f : 0.f, r == 2 * pc + 1 ? 1.f : 0.f);
+}
+
+// Rows [q, q + len) of column pair pc (col points at row q): batches of 8
+// independent loads, the arithmetic in ascending rows, then the stores.
+template <bool LOAD, bool STORE>
+__device__ __forceinline__ void col_pass(float2 *__restrict__ col, int64_t st, int q, int len,
+                                         int pc, const float *const (&v)[4], float ib, float a2,
+                                         float4 &acc)
+{
+    const float s0 = v[2][2 * pc], s1 = v[2][2 * pc + 1], w0 = v[3][2 * pc], w1 = v[3][2 * pc + 1];
+    int r = 0;
+    for (; r + 8 <= len; r += 8) {
+        float2 h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = pass_load<LOAD>(col, st, r + u, q + r + u, pc);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pass_elem<STORE>(h[u], q + r + u, v, s0, s1, w0, w1, ib, a2, acc);
+        if constexpr (STORE) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) col[(int64_t)(r + u) * st] = h[u];
+        }
+    }
+    for (; r < len; ++r) {
+        float2 h = pass_load<LOAD>(col, st, r, q + r, pc);
+        pass_elem<STORE>(h, q + r, v, s0, s1, w0, w1, ib, a2, acc);
+        if constexpr (STORE) col[(int64_t)r * st] = h;
+    }
+}
+
+// One pass over a symmetric d x d matrix S (d even, 8-byte aligned, row-
+// major): S g and S y as column sums (y_r = sum_q S[q][r] v[q] in ascending
+// q per row slice, slices added in order: deterministic) into part[r / 2]
+// = ((S g)_{2k}, (S g)_{2k+1}, (S y)_{2k}, (S y)_{2k+1}) for k < d / 2, and
+// with STORE S + U written back (U as in pass_elem, with ib and a2).
+// LOAD = false takes S = I without reading it.  part holds 2 BLOCK
+// entries; every thread of the block calls it; ends with a barrier.
+template <int BLOCK, bool LOAD, bool STORE>
+__device__ void sym_pass(float *__restrict__ H, int d, const float *const (&v)[4], float ib,
+                         float a2, float4 *part)
 {
     const int t = (int)threadIdx.x;
     const SymSplit sp(d, BLOCK);
@@ -220,11 +182,55 @@ __device__ void sym_rank2(float *__restrict__ H, int d, const float *s, const fl
     int pa, qa0, qa1, pb, qb0, qb1;
     sp.item(t, d, pa, qa0, qa1);
     sp.item(t + BLOCK, d, pb, qb0, qb1);
+    const int La = qa1 - qa0, Lb = qb1 - qb0;
     const int64_t st = sp.cp;
-    col_rank2(H2 + (int64_t)qa0 * st + pa, st, s + qa0, w + qa0, qa1 - qa0, s[2 * pa],
-              s[2 * pa + 1], w[2 * pa], w[2 * pa + 1], ib, a2);
-    col_rank2(H2 + (int64_t)qb0 * st + pb, st, s + qb0, w + qb0, qb1 - qb0, s[2 * pb],
-              s[2 * pb + 1], w[2 * pb], w[2 * pb + 1], ib, a2);
+    float2 *ca = H2 + (int64_t)qa0 * st + pa, *cb = H2 + (int64_t)qb0 * st + pb;
+    const float sa0 = v[2][2 * pa], sa1 = v[2][2 * pa + 1], wa0 = v[3][2 * pa], wa1 = v[3][2 * pa + 1];
+    const float sb0 = v[2][2 * pb], sb1 = v[2][2 * pb + 1], wb0 = v[3][2 * pb], wb1 = v[3][2 * pb + 1];
+    float4 accA = make_float4(0.f, 0.f, 0.f, 0.f), accB = accA;
+    // both streams side by side while both have rows, U loads each in flight
+    // (8 for a read-only pass; 4 when the pass also writes, which needs the
+    // rank-2 operands of both streams in registers)
+    constexpr int U = STORE ? 4 : 8;
+    const int L2 = La < Lb ? La : Lb;
+    int r = 0;
+    for (; r + U <= L2; r += U) {
+        float2 ha[U], hb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ha[u] = pass_load<LOAD>(ca, st, r + u, qa0 + r + u, pa);
+            hb[u] = pass_load<LOAD>(cb, st, r + u, qb0 + r + u, pb);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            pass_elem<STORE>(ha[u], qa0 + r + u, v, sa0, sa1, wa0, wa1, ib, a2, accA);
+            pass_elem<STORE>(hb[u], qb0 + r + u, v, sb0, sb1, wb0, wb1, ib, a2, accB);
+        }
+        if constexpr (STORE) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                ca[(int64_t)(r + u) * st] = ha[u];
+                cb[(int64_t)(r + u) * st] = hb[u];
+            }
+        }
+    }
+    col_pass<LOAD, STORE>(ca + (int64_t)r * st, st, qa0 + r, La - r, pa, v, ib, a2, accA);
+    col_pass<LOAD, STORE>(cb + (int64_t)r * st, st, qb0 + r, Lb - r, pb, v, ib, a2, accB);
+    if (t < sp.items) part[t] = accA;
+    if (t + BLOCK < sp.items) part[t + BLOCK] = accB;
+    __syncthreads();
+    // slice sums in place: entry k < cp is read and written by one thread only
+    for (int k = t; k < sp.cp; k += BLOCK) {
+        float4 acc = part[k];
+        for (int j = 1; j < sp.nq; ++j) {
+            const float4 o = part[j * sp.cp + k];
+            acc.x += o.x;
+            acc.y += o.y;
+            acc.z += o.z;
+            acc.w += o.w;
+        }
+        part[k] = acc;
+    }
     __syncthreads();
 }
 struct NoShared {
@@ -362,7 +368,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             visits = ne > 1;
         }
         // dense: every circle's index inside its batch (ascending circle
-        // index), the batches' matrices H_p = I in this instance's region
+        // index); each batch's matrix and its four vectors (s slots 0 and 1,
+        // y, w) in this instance's region.  The matrices are not written
+        // here: a batch's S stands for I until its first update is applied.
         float *Hbase = nullptr;
         if constexpr (DENSE) {
             visits = true;                   // one batch too: the dense update
@@ -385,9 +393,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     o += d * d;
                 }
                 sq.hoff[A.nbat] = o;
+                for (int q = 0; q < A.nbat; ++q) {
+                    sq.voff[q] = o;
+                    o += 4 * 2 * sq.cnt[q];
+                }
+                sq.voff[A.nbat] = o;
             }
             __syncthreads();
-            if ((int64_t)sq.hoff[A.nbat] > A.hstride) {
+            if ((int64_t)sq.voff[A.nbat] > A.hstride) {
                 if (tid == 0) {
                     DescentResultDev r = {};
                     r.status = 7;  // BAD_INSTANCE: the matrices do not fit the workspace
@@ -398,12 +411,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 }
                 continue;
             }
-            for (int q = 0; q < A.nbat; ++q) {
-                const int d = 2 * sq.cnt[q];
-                float *H = Hbase + sq.hoff[q];
-                for (int e = tid; e < d * d; e += kDB) H[e] = (e / d == e % d) ? 1.f : 0.f;
-            }
-            __syncthreads();
         }
 
         // ---- per-thread state (circle c of this thread is tid + c*kDB) ----
@@ -443,6 +450,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         float gsum = 0.f, gsum_prev = 0.f, E_tot = 0.f;
         int nvis = 0, nstall = 0;
         int anm_cnt = 0, anm_len = 1, anm_it = 0;
+        // dense (lane p: batch p): kDn* flags, 1/beta and a2 of K, beta of Q
+        int dst_v = kDnIdent;
+        float ibK_v = 0.f, a2K_v = 0.f, bQ_v = 0.f;
 
         // relative decrease of the accepted energy over the last W iterations
         // (lane w of ehist holds iteration w mod (W + 1)) at most ftol
@@ -511,93 +521,205 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             return changed;
         };
-        // dense batch descent (Eq. 8-11).  A thread owns rows r = tid,
-        // tid + 512, ... of H_p and reads them as columns (H_p is symmetric),
-        // so every wave's loads are consecutive floats; sums over a batch's
-        // coordinates go lane 0 -> per-wave slot -> every thread in wave
-        // order (deterministic).
-        auto batch_sum = [&](float v) -> float {
-            const int t0 = (int)threadIdx.x;
-            const float w = wave_sum(v);
-            if constexpr (DENSE) {
-                if ((t0 & (kWave - 1)) == 0) sq.wpart[t0 / kWave] = w;
-                __syncthreads();
-                float tsum = 0.f;
-#pragma unroll
-                for (int q = 0; q < kDW; ++q) tsum += sq.wpart[q];
-                __syncthreads();
-                return tsum;
-            } else {
-                return w;
-            }
-        };
-        // stage the batch's components of two per-circle vectors into vb[0], vb[1]
-        auto dense_stage = [&](const float2 (&u)[kCPT], const float2 (&v)[kCPT]) {
+        // dense batch descent (Eq. 8-11).  Each batch's matrix is kept one
+        // update behind: the stored S, a known pending update K = (s_K, w_K,
+        // 1/beta_K, a2_K) and the newest curvature pair Q = (s_Q, y_Q, beta_Q)
+        // whose w = H' y_Q is not formed yet, so that H_p = S + K + Q with
+        // Eq. 11 written as the symmetric rank-2 update
+        //   -(w s' + s w')/beta + (y'w/beta^2 + 1/beta) s s',  w = H' y.
+        // A visit makes one pass over S: it reads S (unless S stands for I),
+        // forms S g and S y_Q, and writes S + K back; (S + K) y_Q = w_Q and
+        // H_p g = (S + K) g + Q g then follow from dot products, and Q
+        // becomes the next K.  One read and one write of the matrix per
+        // visit.  Sums over a batch's coordinates go lane 0 -> per-wave slot
+        // -> every thread in wave order (deterministic).
+        auto batch_sum4 = [&](float4 v) -> float4 {
+            float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
             if constexpr (DENSE) {
                 const int t0 = (int)threadIdx.x;
+                const float s0 = wave_sum(v.x), s1 = wave_sum(v.y), s2 = wave_sum(v.z),
+                            s3 = wave_sum(v.w);
+                if ((t0 & (kWave - 1)) == 0) {
+                    sq.wpart[0][t0 / kWave] = s0;
+                    sq.wpart[1][t0 / kWave] = s1;
+                    sq.wpart[2][t0 / kWave] = s2;
+                    sq.wpart[3][t0 / kWave] = s3;
+                }
+                __syncthreads();
 #pragma unroll
-                for (int c = 0; c < kCPT; ++c) {
-                    const int i = t0 + c * kDB;
-                    if (act[c] && batc_of(c) == cb) {
-                        const int m = sq.memb[i];
-                        sq.vb[0][2 * m] = u[c].x;
-                        sq.vb[0][2 * m + 1] = u[c].y;
-                        sq.vb[1][2 * m] = v[c].x;
-                        sq.vb[1][2 * m + 1] = v[c].y;
-                    }
+                for (int q = 0; q < kDW; ++q) {
+                    r.x += sq.wpart[0][q];
+                    r.y += sq.wpart[1][q];
+                    r.z += sq.wpart[2][q];
+                    r.w += sq.wpart[3][q];
                 }
                 __syncthreads();
             }
+            return r;
         };
         // p = -H_p g on the batch's circles (zero elsewhere); returns g'p
         auto dense_direction = [&]() -> float {
             float gpv = 0.f;
             if constexpr (DENSE) {
-                const int t0 = (int)threadIdx.x;
+                const int t0 = (int)threadIdx.x, ln = t0 & (kWave - 1);
                 const int d = 2 * sq.cnt[cb];
-                const float *H = Hbase + sq.hoff[cb];
-                dense_stage(g, g);
-                sym_matvec<kDB>(H, d, sq.vb[0], sq.vb[2], sq.part);
-                float part = 0.f;
-                for (int r = t0; r < d; r += kDB) part += sq.vb[2][r] * sq.vb[0][r];
-                gpv = -batch_sum(part);
+                float *H = Hbase + sq.hoff[cb];
+                float *V = Hbase + sq.voff[cb];
+                const int fl = __builtin_amdgcn_readlane(dst_v, cb);
+                const bool ident = fl & kDnIdent, hasK = fl & kDnK, hasQ = fl & kDnQ;
+                const int ks = (fl & kDnSlot) ? 1 : 0;
+                const float ibK = lane_value(ibK_v, cb), a2K = lane_value(a2K_v, cb);
+                const float2 *sK = reinterpret_cast<const float2 *>(V + ks * d);
+                const float2 *sQ = reinterpret_cast<const float2 *>(V + (ks ^ 1) * d);
+                const float2 *yQ = reinterpret_cast<const float2 *>(V + 2 * d);
+                float2 *wK = reinterpret_cast<float2 *>(V + 3 * d);
+                const float2 z2 = make_float2(0.f, 0.f);
+                // stage g, y_Q, s_K, w_K (zeros where absent)
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = t0 + c * kDB;
                     if (act[c] && batc_of(c) == cb) {
                         const int m = sq.memb[i];
-                        p[c] = make_float2(-sq.vb[2][2 * m], -sq.vb[2][2 * m + 1]);
-                    } else {
-                        p[c] = make_float2(0.f, 0.f);
+                        const float2 yv = hasQ ? yQ[m] : z2;
+                        const float2 sv = hasK ? sK[m] : z2;
+                        const float2 wvv = hasK ? wK[m] : z2;
+                        sq.vb[0][2 * m] = g[c].x;
+                        sq.vb[0][2 * m + 1] = g[c].y;
+                        sq.vb[1][2 * m] = yv.x;
+                        sq.vb[1][2 * m + 1] = yv.y;
+                        sq.vb[2][2 * m] = sv.x;
+                        sq.vb[2][2 * m + 1] = sv.y;
+                        sq.vb[3][2 * m] = wvv.x;
+                        sq.vb[3][2 * m + 1] = wvv.y;
                     }
                 }
+                __syncthreads();
+                const float *const vv[4] = {sq.vb[0], sq.vb[1], sq.vb[2], sq.vb[3]};
+                const bool pass = !ident || hasK;
+                if (ident && hasK) sym_pass<kDB, false, true>(H, d, vv, ibK, a2K, sq.part);
+                else if (hasK) sym_pass<kDB, true, true>(H, d, vv, ibK, a2K, sq.part);
+                else if (pass) sym_pass<kDB, true, false>(H, d, vv, ibK, a2K, sq.part);
+                // S g, S y_Q of this thread's circles; K's dot products
+                float2 Hg[kCPT], wq[kCPT];
+                float4 dk = make_float4(0.f, 0.f, 0.f, 0.f);   // s_K'g, w_K'g, s_K'y_Q, w_K'y_Q
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    Hg[c] = wq[c] = z2;
+                    const int i = t0 + c * kDB;
+                    if (act[c] && batc_of(c) == cb) {
+                        const int m = sq.memb[i];
+                        const float2 yv = make_float2(sq.vb[1][2 * m], sq.vb[1][2 * m + 1]);
+                        if (pass) {
+                            const float4 pr = sq.part[m];
+                            Hg[c] = make_float2(pr.x, pr.y);
+                            wq[c] = make_float2(pr.z, pr.w);
+                        } else {
+                            Hg[c] = g[c];
+                            wq[c] = yv;
+                        }
+                        const float2 sv = make_float2(sq.vb[2][2 * m], sq.vb[2][2 * m + 1]);
+                        const float2 wvv = make_float2(sq.vb[3][2 * m], sq.vb[3][2 * m + 1]);
+                        dk.x += sv.x * g[c].x + sv.y * g[c].y;
+                        dk.y += wvv.x * g[c].x + wvv.y * g[c].y;
+                        dk.z += sv.x * yv.x + sv.y * yv.y;
+                        dk.w += wvv.x * yv.x + wvv.y * yv.y;
+                    }
+                }
+                // (S + K) g and (S + K) y_Q
+                if (hasK) {
+                    dk = batch_sum4(dk);
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        const int i = t0 + c * kDB;
+                        if (act[c] && batc_of(c) == cb) {
+                            const int m = sq.memb[i];
+                            const float2 sv = make_float2(sq.vb[2][2 * m], sq.vb[2][2 * m + 1]);
+                            const float2 wvv = make_float2(sq.vb[3][2 * m], sq.vb[3][2 * m + 1]);
+                            Hg[c].x += -(wvv.x * dk.x + sv.x * dk.y) * ibK + a2K * sv.x * dk.x;
+                            Hg[c].y += -(wvv.y * dk.x + sv.y * dk.y) * ibK + a2K * sv.y * dk.x;
+                            wq[c].x += -(wvv.x * dk.z + sv.x * dk.w) * ibK + a2K * sv.x * dk.z;
+                            wq[c].y += -(wvv.y * dk.z + sv.y * dk.w) * ibK + a2K * sv.y * dk.z;
+                        }
+                    }
+                }
+                int nf = fl & ~(kDnIdent | kDnK);
+                if (!pass) nf |= kDnIdent;
+                if (hasQ) {
+                    // Q's update with w_Q = (S + K) y_Q; Q becomes K
+                    float4 dq = make_float4(0.f, 0.f, 0.f, 0.f);  // y_Q'w_Q, s_Q'g, w_Q'g
+                    float2 sqv[kCPT];
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        sqv[c] = z2;
+                        const int i = t0 + c * kDB;
+                        if (act[c] && batc_of(c) == cb) {
+                            const int m = sq.memb[i];
+                            const float2 yv = make_float2(sq.vb[1][2 * m], sq.vb[1][2 * m + 1]);
+                            sqv[c] = sQ[m];
+                            dq.x += yv.x * wq[c].x + yv.y * wq[c].y;
+                            dq.y += sqv[c].x * g[c].x + sqv[c].y * g[c].y;
+                            dq.z += wq[c].x * g[c].x + wq[c].y * g[c].y;
+                        }
+                    }
+                    dq = batch_sum4(dq);
+                    const float ibQ = 1.f / lane_value(bQ_v, cb);
+                    const float a2Q = dq.x * ibQ * ibQ + ibQ;
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        const int i = t0 + c * kDB;
+                        if (act[c] && batc_of(c) == cb) {
+                            const int m = sq.memb[i];
+                            Hg[c].x += -(wq[c].x * dq.y + sqv[c].x * dq.z) * ibQ + a2Q * sqv[c].x * dq.y;
+                            Hg[c].y += -(wq[c].y * dq.y + sqv[c].y * dq.z) * ibQ + a2Q * sqv[c].y * dq.y;
+                            wK[m] = wq[c];
+                        }
+                    }
+                    nf = (nf & ~(kDnQ | kDnSlot)) | kDnK | (ks ? 0 : kDnSlot);
+                    ibK_v = ln == cb ? ibQ : ibK_v;
+                    a2K_v = ln == cb ? a2Q : a2K_v;
+                }
+                dst_v = ln == cb ? nf : dst_v;
+                float part = 0.f;
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    if (act[c] && batc_of(c) == cb) {
+                        part += g[c].x * Hg[c].x + g[c].y * Hg[c].y;
+                        p[c] = make_float2(-Hg[c].x, -Hg[c].y);
+                    } else {
+                        p[c] = z2;
+                    }
+                }
+                gpv = -batch_sum4(make_float4(part, 0.f, 0.f, 0.f)).x;
             }
             return gpv;
         };
-        // Eq. 11 with u = s, v = y, beta = s'y:
-        //   H <- H - (w s' + s w')/beta + (y'w/beta^2 + 1/beta) s s',  w = H y
-        auto dense_update = [&](float beta, const float2 (&s_)[kCPT], const float2 (&y_)[kCPT]) {
+        // an accepted step with s'y > eps_curv y'y becomes the batch's Q
+        auto dense_record = [&](float beta, const float2 (&s_)[kCPT], const float2 (&y_)[kCPT]) {
             if constexpr (DENSE) {
-                const int t0 = (int)threadIdx.x;
+                const int t0 = (int)threadIdx.x, ln = t0 & (kWave - 1);
                 const int d = 2 * sq.cnt[cb];
-                float *H = Hbase + sq.hoff[cb];
-                dense_stage(s_, y_);
-                sym_matvec<kDB>(H, d, sq.vb[1], sq.vb[2], sq.part);
-                float part = 0.f;
-                for (int r = t0; r < d; r += kDB) part += sq.vb[2][r] * sq.vb[1][r];
-                const float yw = batch_sum(part);
-                const float ib = 1.f / beta;
-                const float a2 = yw * ib * ib + ib;
-                sym_rank2<kDB>(H, d, sq.vb[0], sq.vb[2], ib, a2);
+                float *V = Hbase + sq.voff[cb];
+                const int fl = __builtin_amdgcn_readlane(dst_v, cb);
+                float2 *sQ = reinterpret_cast<float2 *>(V + ((fl & kDnSlot) ? 0 : 1) * d);
+                float2 *yQ = reinterpret_cast<float2 *>(V + 2 * d);
+#pragma unroll
+                for (int c = 0; c < kCPT; ++c) {
+                    const int i = t0 + c * kDB;
+                    if (act[c] && batc_of(c) == cb) {
+                        const int m = sq.memb[i];
+                        sQ[m] = s_[c];
+                        yQ[m] = y_[c];
+                    }
+                }
+                dst_v = ln == cb ? (fl | kDnQ) : dst_v;
+                bQ_v = ln == cb ? beta : bQ_v;
             }
         };
+        // H_p = I: nothing pending, S stands for I again
         auto dense_reset = [&]() {
             if constexpr (DENSE) {
-                const int d = 2 * sq.cnt[cb];
-                float *H = Hbase + sq.hoff[cb];
-                __syncthreads();
-                for (int e = (int)threadIdx.x; e < d * d; e += kDB) H[e] = (e / d == e % d) ? 1.f : 0.f;
-                __syncthreads();
+                const int ln = (int)threadIdx.x & (kWave - 1);
+                dst_v = ln == cb ? kDnIdent : dst_v;
             }
         };
 
@@ -998,7 +1120,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     // wave has finished with B), then the next batch
                     kb_v = lane == cb ? k : kb_v;
                     if constexpr (DENSE) {
-                        if (push) dense_update(lane_value(tot, sScYc), sc, yc);
+                        if (push) dense_record(lane_value(tot, sScYc), sc, yc);
                     } else {
                         __syncthreads();
 #pragma unroll
