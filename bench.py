@@ -228,7 +228,7 @@ def descent_params(P, max_iter):
 
 
 def algorithmic_flops(res, n, m):
-    """Flops the method needs for the recorded work (see DESIGN.md):
+    """Flops the method needs for the recorded work:
     10 per listed pair (i<j) and 10 per circle per evaluation, and the
     L-BFGS two-loop (16 m n) plus the curvature update (8 n) per iteration."""
     return float((10.0 * res["pair_evals"] + 10.0 * n * res["evals"]

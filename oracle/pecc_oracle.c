@@ -494,7 +494,7 @@ int oracle_verify(int n, const float *xy, double R, double tol, double *out)
 /* Geometric batch descent (Alg. 1) with the limited-memory reading of      */
 /* Eq. 8-11, the batch energy of Eq. 7 and a 2D grid-block partition.       */
 /*                                                                           */
-/* Partition (Alg. 1 line 1), fixed for the whole descent: block side        */
+/* Partition (the first step of Alg. 1), fixed for the whole descent: block  */
 /* S = 2R / blocks over [-R, R]^2; circle i goes to block (bx, by) with      */
 /* bx = clamp(floor((x_i + R) / S), 0, blocks-1) (likewise by), batch id     */
 /* p = by * blocks + bx, colour (bx mod 2) + 2 (by mod 2).  Batches are       */
@@ -513,7 +513,7 @@ int oracle_verify(int n, const float *xy, double R, double tol, double *out)
 /* (the GPU rebuilds its neighbor lists at that point).  A visit whose line  */
 /* search fails leaves the batch unchanged.                                  */
 /*                                                                           */
-/* Outer iteration (Alg. 1 lines 5-16) stop tests, at its top: non-finite   */
+/* Outer iteration of Alg. 1: stop tests at its top: non-finite              */
 /* E, E < e_feasible, sum over batches of ||g(x_p)||_2 of the previous outer */
 /* iteration <= g_tol, relative decrease of E over ftol_window outer        */
 /* iterations <= ftol, max_outer reached.                                    */

@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                         return wave_reduce_scatter<kGCPB>(gt, sc, yc, S, Y, e, e1);
                     };
 
-                    // ---- gradient at the start of the visit (Alg. 1 line 7) -----
+                    // ---- gradient at the start of the visit (Alg. 1) -----
                     float2 gt[kGCPB], yc[kGCPB], sc0[kGCPB];
 #pragma unroll
                     for (int c = 0; c < kGCPB; ++c) sc0[c] = make_float2(0.f, 0.f);

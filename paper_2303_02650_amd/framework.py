@@ -2,10 +2,10 @@
 a batch of independent runs ("chains"), each with its own reference radius
 R_b.  It only sequences library calls and keeps the best record:
 
-  line 1-3   x* = random layout in [-R_b, R_b]^2, descended at R_b
+  start      x* = random layout in [-R_b, R_b]^2, descended at R_b
              (pecc_lbfgs_descend), then the container adjustment of Alg. 2
              (pecc_adjust_container) gives (x*, R*);
-  line 4-11  per round: R = min(R_b, R*); SED (Alg. 5) from a new random
+  rounds     per round: R = min(R_b, R*); SED (Alg. 5) from a new random
              layout at R (SedChains: descent, J-controlled candidates,
              Eq. 18 selection, stop at E <= 1e-25); the adjustment of its
              best layout gives (x, R'); the record takes (x, R') when R' <
@@ -30,7 +30,7 @@ from .sed import SedChains
 
 
 def _random_layouts(n: int, R: np.ndarray, seed: int, round_: int) -> np.ndarray:
-    """Uniform layouts in [-R_c, R_c]^2 (Alg. 4 line 1, Alg. 5 line 1)."""
+    """Uniform layouts in [-R_c, R_c]^2 (the initial layouts of Alg. 4 and Alg. 5)."""
     out = []
     for c, Rc in enumerate(R):
         rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, round_, c])))
@@ -49,7 +49,7 @@ class Framework:
         self.offset = np.arange(self.C + 1, dtype=np.int32) * n
         self.rounds = 0
         self.history = []
-        # lines 1-3
+        # start: descent and container adjustment of a random layout
         x = torch.from_numpy(_random_layouts(n, self.R_b, seed, 0)).to(self.dev).reshape(-1)
         inst = self._instances(self.R_b)
         out = torch.empty(self.C * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
@@ -73,7 +73,7 @@ class Framework:
         return feas.cpu().numpy().astype(bool)
 
     def step(self) -> dict:
-        """One round of lines 5-10 for every chain."""
+        """One round of Alg. 4 for every chain."""
         t = self.rounds + 1
         R = np.minimum(self.R_b, self.R_best)
         inst = self._instances(R)

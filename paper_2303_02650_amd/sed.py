@@ -27,7 +27,7 @@ class SedChains:
         self.inst, self.M, self.e_stop, self.seed = inst, M, e_stop, seed
         self.P = (params or DescentParams()).c()
         self.xy = xy.reshape(-1).contiguous()
-        # lines 1-3 of Alg. 5: descend the starts
+        # Alg. 5 begins by descending the starts
         out = torch.empty(inst.B * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
         ws = torch.empty(pecc_lbfgs_descend_workspace_size(inst), dtype=torch.uint8, device=dev)
         from . import pecc_lbfgs_descend
