@@ -875,14 +875,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             // energy, Eq. 7) from the batch's end
                             bool hf = j > i;
                             if constexpr (SEQ) if (masked) hf = hf || sq.bat[j] != cb;
-                            pair_term32(q, pj[c], hf, two_r, four_r2, ecA[c], e1cA[c], gxA[c], gyA[c]);
+                            float l2;
+                            const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
+                                                          ecA[c], e1cA[c], gxA[c], gyA[c], l2);
                             // FP64 energies only where FP32 sees (nearly) an overlap:
                             // outside a 1e-5 band the FP64 terms are zero
-                            if (want64 && hf) {
-                                const float dx = q.x - pj[c].x, dy = q.y - pj[c].y;
-                                if (dx * dx + dy * dy < four_r2_band)
-                                    pair_term64(q, pj[c], two_r64, four_r2_64, eocA[c], etcA[c]);
-                            }
+                            if (want64 && hf && l2 < four_r2_band)
+                                pair_term64s(q, pj[c], l2 * il, il, two_r64, four_r2_64, eocA[c], etcA[c]);
                         }
                     }
                 }
@@ -937,7 +936,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     gx += kc * q.x;
                     gy += kc * q.y;
                     if (want64) {
-                        const double r64 = sqrt((double)q.x * q.x + (double)q.y * q.y);
+                        const double r64 =
+                            sqrt64_from32((double)q.x * q.x + (double)q.y * q.y, r2 * ir, ir);
                         const double c0 = r64 + rad64 - R64;
                         if (c0 > 0.0) eo += c0 * c0;
                         const double ct = r64 + 1.0 - R64;
@@ -956,7 +956,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             const float wsum = wave_reduce_scatter(gt, sc, yc, S, Y, e, e1);
             sh.red[par][wv][lane_slot(lane)] = wsum;
             if (want64) {
-                const double wo = wave_sum(eo), wt = wave_sum(et);
+                const double wo = wave_sum_dpp(eo), wt = wave_sum_dpp(et);
                 if (lane == 0) { sh.red64[par][wv][0] = wo; sh.red64[par][wv][1] = wt; }
             }
             __syncthreads();                                            // B2

@@ -111,6 +111,30 @@ __device__ __forceinline__ float wave_sum_dpp(float v)
     return lane_value(v, 63);
 }
 
+// The same sum for a double: each DPP step moves the two 32-bit halves.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp64<kDppXor1>(v);
+    v += dpp64<kDppXor2>(v);
+    v += dpp64<kDppHalfMirror>(v);
+    v += dpp64<kDppRowMirror>(v);
+    v += dpp64<kDppBcast15, 0xa>(v);
+    v += dpp64<kDppBcast31, 0xc>(v);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Slot held by lane L after wave_reduce_scatter (stages decided by lane bits
 // 3, 2, 1, 0, 4, 5 in this order).
 __device__ __forceinline__ int lane_slot(int L)
@@ -263,6 +287,59 @@ __device__ __forceinline__ void pair_term64(float2 q, float2 pj, double two_r64,
     const double m2 = ex * ex + ey * ey;
     if (m2 < four_r2_64) {
         const double l = sqrt(m2);
+        const double d = two_r64 - l;
+        const double dt = m2 < 4.0 ? 2.0 - l : 0.0;
+        eo += d * d;
+        et += dt * dt;
+    }
+}
+
+// sqrt(m2) in FP64 from FP32 estimates l32 ~ sqrt(m2) and il ~ 1/sqrt(m2)
+// (both 0 when m2 is 0): two Newton steps l <- l + (m2 - l^2) * il / 2, the
+// residual formed with one rounding.  With relative errors e of l32 and h
+// of il, one step leaves about e^2 / 2 + e h (1e-14 from 1e-7) and the
+// second one FP64 rounding: a square root without the FP64 reciprocal
+// square root, whose seed is no better than il.
+__device__ __forceinline__ double sqrt64_from32(double m2, float l32, float il)
+{
+    const double h = (double)(0.5f * il);
+    double l = (double)l32;
+    l = fma(fma(-l, l, m2), h, l);
+    l = fma(fma(-l, l, m2), h, l);
+    return l;
+}
+
+// pair_term32 that also returns the FP32 1/l of pairs inside the FP64 band
+// (l2 < four_r2_band, 0 elsewhere and at l2 = 0) and l2, the seeds of
+// pair_term64s.  The FP32 terms are those of pair_term32, bit for bit.
+__device__ __forceinline__ float pair_term32s(float2 q, float2 pj, bool count_e, float two_r,
+                                              float four_r2, float four_r2_band, float &e,
+                                              float &e1, float &gx, float &gy, float &l2o)
+{
+    const float dx = q.x - pj.x, dy = q.y - pj.y;
+    const float l2 = dx * dx + dy * dy;
+    const bool ov = l2 < four_r2;
+    const float il = (l2 < four_r2_band && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
+    const float d = ov ? two_r - l2 * il : 0.f;
+    const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
+    e += count_e ? d * d : 0.f;
+    e1 += count_e ? d1 * d1 : 0.f;
+    const float kf = -2.f * d * il;
+    gx += kf * dx;
+    gy += kf * dy;
+    l2o = l2;
+    return il;
+}
+
+// pair_term64 with the square root from the FP32 seeds (l32 = l2 * il).
+__device__ __forceinline__ void pair_term64s(float2 q, float2 pj, float l32, float il,
+                                             double two_r64, double four_r2_64, double &eo,
+                                             double &et)
+{
+    const double ex = (double)q.x - (double)pj.x, ey = (double)q.y - (double)pj.y;
+    const double m2 = ex * ex + ey * ey;
+    if (m2 < four_r2_64) {
+        const double l = sqrt64_from32(m2, l32, il);
         const double d = two_r64 - l;
         const double dt = m2 < 4.0 ? 2.0 - l : 0.0;
         eo += d * d;

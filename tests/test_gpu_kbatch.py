@@ -149,7 +149,7 @@ def test_anm_defers_on_a_stationary_pair(P):
 
 @pytest.mark.parametrize("anm", [False, True])
 def test_descents_finish_like_oracle(P, anm):
-    inst = synth.C4(8)
+    inst = synth.C4(32)
     bo = host_partition(inst, "sector", 5)
     params = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4,
                              cutoff=4.0 if anm else 2.3)
@@ -159,15 +159,17 @@ def test_descents_finish_like_oracle(P, anm):
     status = [P.STATUS[s] for s in res["status"]]
     info = list(zip(status, res["iters"].tolist(), res["E32"].tolist()))
     assert set(status) <= {"FEASIBLE", "CONVERGED", "STATIONARY", "STALLED", "MAX_ITER"}, info
-    assert status.count("MAX_ITER") <= 2, info
+    assert status.count("MAX_ITER") <= 8, info
     # outcomes in the oracle's range: E64 of the final layouts, and the
     # outer iterations of an FP64 descent from the same start
     e_gpu = np.array([oracle.verify(xg[inst.offset[b]:inst.offset[b + 1]], float(inst.R[b]))["E"]
                       for b in range(inst.B)])
     # every layout far below its start (E0 > 1000), some of them feasible;
-    # at this density the others are jammed local minima
+    # at this density the others are jammed local minima.  About a quarter
+    # of such starts end feasible with five sector batches (256-start
+    # study); at that rate fewer than 3 of 32 has probability about 0.5 %
     assert e_gpu.max() < 1e-3 * float(oracle.energy(inst.instance(0).astype(np.float64), inst.R[0]))
-    assert (e_gpu < 1e-20).mean() >= 0.25, (e_gpu, info)
+    assert (e_gpu < 1e-20).sum() >= 3, (e_gpu, info)
     o0, o1 = inst.offset[0], inst.offset[1]
     _, r64, _ = oracle.gbo_seq_descend(inst.instance(0).astype(np.float64), inst.R[0], bo[o0:o1],
                                        5, oracle.DescentParams(g_tol=1e-12, ftol=1e-9),
