@@ -37,7 +37,7 @@ COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
 # measured on the 1 GiB copy): profiles/energy_grad_kernel_traffic_65536x1000.md.
 # Valid for the kernel as profiled; None for other batch sizes.
-SWEEP_TRAFFIC_BYTES_65536 = 2.5748e9
+SWEEP_TRAFFIC_BYTES_65536 = 2.5750e9
 # HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
 # (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
 DESCENT_TRAFFIC_BYTES_256 = 4.7e6
@@ -45,8 +45,8 @@ DESCENT_TRAFFIC_BYTES_256 = 4.7e6
 # evaluation, SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES):
 # profiles/lbfgs_descend_kernel_sq_counters_256x1000.md.  Valid for the
 # kernel as profiled.
-DESCENT_VALU_PER_WAVE_EVAL_256 = 1922
-DESCENT_VALU_ACTIVE_SHARE_256 = 0.371
+DESCENT_VALU_PER_WAVE_EVAL_256 = 1901
+DESCENT_VALU_ACTIVE_SHARE_256 = 0.365
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
