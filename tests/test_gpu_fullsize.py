@@ -40,6 +40,12 @@ def test_main_step_full_size_sampled(P):
     # FEASIBLE claims hold in FP64, and feasible means E64 < 1e-20
     assert (feas[res["status"] == 1] == 1).all()
     assert ((e64 < 1e-20) == (feas == 1)).all()
+    # the FP64 unit-circle energies the descent reports (FP64 regime: its
+    # band terms with square roots refined from FP32 seeds) agree with the
+    # brute-force FP64 check of the same layouts to FP64 accuracy
+    m = res["E64"] >= 0
+    assert m.sum() >= 200
+    np.testing.assert_allclose(res["E64"][m], e64[m], rtol=1e-6, atol=1e-22)
     # sampled instances against the oracle
     for b in range(0, 256, 37):
         xb = x[inst.offset[b]:inst.offset[b + 1]]
