@@ -241,7 +241,7 @@ class DescentParams:
     ftol: float = 1e-7
     contact_margin: float = 0.0
     e_feasible: float = 1e-20
-    tau64: float = 1e-4
+    tau64: float = 1e-5
 
     def c(self) -> pecc_descent_params:
         return pecc_descent_params(**asdict(self))
