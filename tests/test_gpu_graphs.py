@@ -145,3 +145,42 @@ def test_partition_and_kbatch_descents_graph_replays(P):
             assert torch.equal(a, b), rep
         P.partition(d, x0, "fence", 2)                   # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_concurrent_launches_on_several_streams_match_sequential(P):
+    """The same descents and verifies issued on four streams at once (own
+    buffers per stream, two rounds, plain launches): every stream's results
+    equal the sequential run's bit for bit, whichever workgroups and CUs the
+    overlapping persistent launches got."""
+    inst = synth.C2(64)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    x0 = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4).c()
+    nws = P.pecc_lbfgs_descend_workspace_size(d)
+
+    def buffers():
+        return (torch.empty_like(x0), torch.zeros(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                                                  device="cuda"),
+                torch.empty(nws, dtype=torch.uint8, device="cuda"),
+                torch.zeros(d.B, dtype=torch.float64, device="cuda"),
+                torch.zeros(d.B, dtype=torch.int32, device="cuda"))
+
+    def step(b):
+        x, out, ws, e64, feas = b
+        x.copy_(x0)
+        P.pecc_lbfgs_descend(d, x, prm, out, ws)
+        P.pecc_verify(d, x, 1e-20, e64, None, None, feas)
+
+    ref = buffers()
+    step(ref)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    sets = [buffers() for _ in streams]
+    for _ in range(2):
+        for st, b in zip(streams, sets):
+            with torch.cuda.stream(st):
+                step(b)
+    torch.cuda.synchronize()
+    for k, b in enumerate(sets):
+        for got, want in zip(b[:2] + b[3:], ref[:2] + ref[3:]):
+            assert torch.equal(got, want), k
