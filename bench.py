@@ -395,6 +395,9 @@ def main():
             "valu_instructions_per_wave_eval": DESCENT_VALU_PER_WAVE_EVAL_256 if a.batch == 256 else None,
             "valu_active_share_of_wave_time": DESCENT_VALU_ACTIVE_SHARE_256 if a.batch == 256 else None,
             "busy_cu_share": float(res["iters"].mean() / max(1, res["iters"].max()))}
+    # the same fraction over the CU time the descents actually hold (one
+    # instance per CU; a CU idles once its descent has ended)
+    roof["frac_of_busy_cus"] = roof["frac"] / max(roof["busy_cu_share"], 1e-9)
 
     line = {
         "metric": "L-BFGS descents/sec at n=1000 (batched FP32, persistent launch), to E<1e-20 or convergence",
