@@ -423,41 +423,6 @@ def main():
         line["autotune"] = {"chosen": main_tune["best"], "sample_instances": 64,
                             "table": main_tune["table"]}
 
-    # ---- the same steps pipelined over streams -----------------------------
-    # Consecutive steps (each the same 256 starts: reset, one persistent
-    # launch, its verify, own buffers) on a ring of streams: a launch's
-    # workgroups leave their CU once its queue is empty, so the next
-    # launches' work fills the CUs that a step's slowest descents leave idle.
-    # Every descent runs to its end and every result is checked against the
-    # timed step's.  Plain launches, not graph replays: replays of captured
-    # graphs on more streams than the device has hardware queues were seen
-    # to overlap consecutive replays on one stream.
-    if a.pipeline_streams > 1:
-        sets = []
-        for _ in range(a.pipeline_streams):
-            sets.append((torch.cuda.Stream(), torch.empty_like(xy0), torch.empty_like(out),
-                         torch.empty_like(ws), torch.empty_like(e64), torch.empty_like(mp_),
-                         torch.empty_like(mc_), torch.empty_like(feas)))
-        torch.cuda.synchronize()
-        kp = a.steps * a.pipeline_streams
-        t0 = time.perf_counter()
-        for k in range(kp):
-            st, xs, outs, wss, e64s, mps, mcs, fes = sets[k % len(sets)]
-            with torch.cuda.stream(st):
-                xs.copy_(xy0)
-                P.pecc_lbfgs_descend(d, xs, Pc, outs, wss)
-                P.pecc_verify(d, xs, 1e-20, e64s, mps, mcs, fes)
-        torch.cuda.synchronize()
-        wall_p = time.perf_counter() - t0
-        same = all(torch.equal(xs, xy) and torch.equal(outs, out) and torch.equal(fes, feas)
-                   for _, xs, outs, _, _, _, _, fes in sets)
-        line["pipelined"] = {
-            "streams": len(sets), "steps": kp, "ms_per_step": wall_p * 1e3 / kp,
-            "descents_per_s": a.batch * kp / wall_p, "results_equal_to_timed_step": bool(same),
-            "note": "the same step on a ring of streams; not the headline value"}
-        print(f"[bench] pipelined over {len(sets)} streams: {wall_p * 1e3 / kp:.2f} ms/step, "
-              f"results equal: {same}", file=sys.stderr, flush=True)
-
     # ---- ablation of the FP64 threshold of the sufficient-decrease test ----
     # The FP64 regime starts once min(E32, E1) < tau64; tau64 = 0 keeps every
     # test in FP32.  Same starts, one launch each, FP64 verify of the results.
@@ -893,6 +858,42 @@ def main():
         print(f"[bench] sweep: {dbig.B} instances, {bytes_alg / 1e9:.2f} GB in {t * 1e3:.3f} ms "
               f"= {gbs:.0f} GB/s", file=sys.stderr, flush=True)
         del big, dbig, xb, row, col, E, g
+
+    # ---- the same steps pipelined over streams -----------------------------
+    # Consecutive steps (each the same 256 starts: reset, one persistent
+    # launch, its verify, own buffers) on a ring of streams: a launch's
+    # workgroups leave their CU once its queue is empty, so the next
+    # launches' work fills the CUs that a step's slowest descents leave idle.
+    # Every descent runs to its end and every result is checked against the
+    # timed step's.  Last of the GPU sections, so that its extra streams
+    # cannot touch the graph replays of the others.  Plain launches, not graph replays: replays of captured
+    # graphs on more streams than the device has hardware queues were seen
+    # to overlap consecutive replays on one stream.
+    if a.pipeline_streams > 1:
+        sets = []
+        for _ in range(a.pipeline_streams):
+            f64 = [torch.empty(d.B, dtype=torch.float64, device=dev) for _ in range(3)]
+            sets.append((torch.cuda.Stream(), torch.empty_like(xy0), torch.empty_like(out),
+                         torch.empty_like(ws), *f64, torch.empty_like(feas)))
+        torch.cuda.synchronize()
+        kp = a.steps * a.pipeline_streams
+        t0 = time.perf_counter()
+        for k in range(kp):
+            st, xs, outs, wss, e64s, mps, mcs, fes = sets[k % len(sets)]
+            with torch.cuda.stream(st):
+                xs.copy_(xy0)
+                P.pecc_lbfgs_descend(d, xs, Pc, outs, wss)
+                P.pecc_verify(d, xs, 1e-20, e64s, mps, mcs, fes)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t0
+        same = all(torch.equal(xs, xy) and torch.equal(outs, out) and torch.equal(fes, feas)
+                   for _, xs, outs, _, _, _, _, fes in sets)
+        line["pipelined"] = {
+            "streams": len(sets), "steps": kp, "ms_per_step": wall_p * 1e3 / kp,
+            "descents_per_s": a.batch * kp / wall_p, "results_equal_to_timed_step": bool(same),
+            "note": "the same step on a ring of streams; not the headline value"}
+        print(f"[bench] pipelined over {len(sets)} streams: {wall_p * 1e3 / kp:.2f} ms/step, "
+              f"results equal: {same}", file=sys.stderr, flush=True)
 
     # ---- FP64 oracle on the host cores (bounded sample) --------------------
     if not a.no_cpu:
