@@ -12,6 +12,13 @@ R_b.  It only sequences library calls and keeps the best record:
              R* and the unit circles are overlap-free at R' in FP64
              (pecc_verify with R' as the FP64 radius).
 
+Every adjusted radius is then tightened in FP64: the descents work on
+circles of radius 1 + contact_margin, so R' keeps up to that margin of
+slack; the smallest container of the layout's unit circles is
+max_i |c_i| + 1 (pecc_verify at radius 0 reports it as the largest
+containment overlap), rounded up to an FP32 value, and it replaces R' where
+the unit circles are pairwise overlap-free in FP64 at it.
+
 The random layouts are drawn here with numpy (chain c, round t: a PCG64
 stream seeded by (seed, t, c)) and passed to the library as inputs; SED
 draws its perturbations with Philox inside the library (seed + round).  Rounds run until ``rounds``
@@ -55,22 +62,41 @@ class Framework:
         out = torch.empty(self.C * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=self.dev)
         ws = torch.empty(pecc_lbfgs_descend_workspace_size(inst), dtype=torch.uint8, device=self.dev)
         pecc_lbfgs_descend(inst, x, self.params.c(), out, ws)
+        self.tightened = 0
         R_adj, _ = adjust_container(inst, x, self.params)
-        ok = self._feasible_at(x, R_adj)
-        self.R_best = np.where(ok, R_adj.cpu().numpy().astype(np.float64), np.inf)
+        R_t, ok = self._tighten(x, R_adj)
+        self.R_best = np.where(ok, R_t, np.inf)
         self.x_best = x.clone()
         self.R_initial = self.R_best.copy()
 
     def _instances(self, R: np.ndarray) -> DeviceInstances:
         return DeviceInstances.from_host(self.offset, np.asarray(R, dtype=np.float32))
 
-    def _feasible_at(self, x: torch.Tensor, R: torch.Tensor) -> np.ndarray:
-        """Unit circles overlap-free (FP64 E < 1e-20) at the FP32 radii R."""
+    def _verify_at(self, x: torch.Tensor, R: torch.Tensor):
         off = torch.from_numpy(self.offset).to(self.dev)
         inst = DeviceInstances(offset=off, R=R.float().contiguous(), R64=R.double().contiguous(),
                                max_n=self.n, total_n=self.C * self.n)
-        _, _, _, feas = verify(inst, x)
-        return feas.cpu().numpy().astype(bool)
+        return verify(inst, x)
+
+    def _feasible_at(self, x: torch.Tensor, R: torch.Tensor) -> np.ndarray:
+        """Unit circles overlap-free (FP64 E < 1e-20) at the FP32 radii R."""
+        return self._verify_at(x, R)[3].cpu().numpy().astype(bool)
+
+    def _tighten(self, x: torch.Tensor, R_adj: torch.Tensor):
+        """Adjusted radii and their FP64 feasibility, each radius replaced by
+        the FP32 value just above max_i |c_i| + 1 where the unit circles
+        are overlap-free in FP64 at that value and it is smaller."""
+        Ra = R_adj.cpu().numpy().astype(np.float64)
+        ok = self._feasible_at(x, R_adj)
+        zero = torch.zeros(self.C, dtype=torch.float64, device=self.dev)
+        Rmin = self._verify_at(x, zero)[2].cpu().numpy()          # max_i fl(|c_i| + 1)
+        Rt = Rmin.astype(np.float32)
+        up = Rt.astype(np.float64) < Rmin
+        Rt[up] = np.nextafter(Rt[up], np.float32(np.inf))
+        ok_t = self._feasible_at(x, torch.from_numpy(Rt).to(self.dev))
+        use = ok_t & (Rt.astype(np.float64) < Ra)
+        self.tightened += int(use.sum())
+        return np.where(use, Rt.astype(np.float64), Ra), ok | use
 
     def step(self) -> dict:
         """One round of Alg. 4 for every chain."""
@@ -82,8 +108,7 @@ class Framework:
         info = sed.run(self.s_iter)
         x = sed.xy_best.clone()
         R_adj, _ = adjust_container(inst, x, self.params)
-        ok = self._feasible_at(x, R_adj)
-        Rn = R_adj.cpu().numpy().astype(np.float64)
+        Rn, ok = self._tighten(x, R_adj)
         better = ok & (Rn < self.R_best)
         if better.any():
             sel = torch.from_numpy(np.repeat(better, 2 * self.n)).to(self.dev)
@@ -109,4 +134,4 @@ class Framework:
         torch.cuda.synchronize()
         return {"rounds": self.rounds, "seconds": time.perf_counter() - t0,
                 "R_initial": self.R_initial.tolist(), "R_best": self.R_best.tolist(),
-                "history": self.history}
+                "tightened": self.tightened, "history": self.history}

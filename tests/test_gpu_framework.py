@@ -58,3 +58,26 @@ def test_time_limit_stops(F):
     fw = F(20, [5.3] * 2, M=4, s_iter=5, seed=1)
     info = fw.run(seconds=0.0)
     assert info["rounds"] == 0
+
+
+def test_tightened_radii_are_the_smallest_fp32_containers(F):
+    """Adjusted radii keep up to the contact margin of slack; the FP64
+    tightening replaces them by the FP32 value just above max_i |c_i| + 1
+    where the unit circles stay overlap-free, so recorded radii are never
+    below that bound, are FP64-feasible, and some sit within one FP32 ulp of
+    it."""
+    n = 40
+    fw = F(n, [math.sqrt(n / 0.8)] * 6, M=10, s_iter=10, seed=5)
+    info = fw.run(rounds=2)
+    assert info["tightened"] > 0
+    x = fw.x_best.cpu().numpy().reshape(-1, 2)
+    tight = 0
+    for c in range(fw.C):
+        xc = x[c * n:(c + 1) * n]
+        Rc = info["R_best"][c]
+        assert Rc == float(np.float32(Rc))
+        Rmin = float((np.hypot(xc[:, 0].astype(np.float64), xc[:, 1].astype(np.float64)) + 1.0).max())
+        assert Rc >= Rmin - 1e-12
+        assert oracle.verify(xc, Rc)["E"] < 1e-20
+        tight += Rc - Rmin <= float(np.spacing(np.float32(Rc)))
+    assert tight >= 1
