@@ -296,7 +296,7 @@ def run_cpu_baseline(inst, max_iter, sample, cores, gpu_pairs_per_eval=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported "
               "(instances are independent: a multi-GPU run would shard the batch with no "
               "exchange)", file=sys.stderr)
         sys.exit(2)
