@@ -387,8 +387,10 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_kernel(
 // FP64 verify: every pair of the instance once.  Circle i is paired with
 // the next floor((n-1)/2) circles cyclically (and, for even n, with i+n/2
 // when i < n/2), which visits each unordered pair exactly once and gives
-// every thread the same amount of work.  512 threads per instance, and the
-// partner positions read four at a time, so that LDS latency overlaps.
+// every thread the same amount of work; the positions sit in LDS twice in
+// a row, so partner i + t needs no wrap.  512 threads per instance, partner
+// positions read four at a time so that LDS latency overlaps.  No
+// contraction: products and sums round as written, like the oracle's.
 // ---------------------------------------------------------------------------
 constexpr int kVerifyBlock = 512;
 
@@ -398,7 +400,8 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     double *__restrict__ energy64, double *__restrict__ max_pair,
     double *__restrict__ max_cont, int32_t *__restrict__ feasible)
 {
-    __shared__ float2 pos[kMaxN];
+#pragma clang fp contract(off)
+    __shared__ float2 pos[2 * kMaxN];
     __shared__ double sum_tmp[kVerifyBlock / kWave];
 
     const int b = blockIdx.x;
@@ -412,7 +415,14 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
         }
         return;
     }
-    stage_positions<kVerifyBlock>(xy, off, n, pos);
+    {
+        const float2 *src = reinterpret_cast<const float2 *>(xy) + off;
+        for (int i = threadIdx.x; i < n; i += kVerifyBlock) {
+            const float2 v = src[i];
+            pos[i] = v;
+            pos[i + n] = v;
+        }
+    }
     __syncthreads();
     const double Rb = R64 ? R64[b] : (double)R[b];
     double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0;
@@ -422,13 +432,15 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
         const double xi = pos[i].x, yi = pos[i].y;
         const int extra = (even && i < n / 2) ? 1 : 0;
         const int cnt = half + extra;
+        // the overlap branch is rare (never taken once a layout is
+        // feasible): a real branch, not a flattened square root per pair
         auto pair = [&](float2 pj) {
-            const double dx = __dsub_rn(xi, (double)pj.x);
-            const double dy = __dsub_rn(yi, (double)pj.y);
-            const double l2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
-            if (l2 < 4.0) {
-                const double d = __dsub_rn(2.0, sqrt(l2));
-                sp = __dadd_rn(sp, __dmul_rn(d, d));
+            const double dx = xi - (double)pj.x;
+            const double dy = yi - (double)pj.y;
+            const double l2 = dx * dx + dy * dy;
+            if (__builtin_expect(l2 < 4.0, 0)) {
+                const double d = 2.0 - sqrt(l2);
+                sp = sp + d * d;
                 mp = fmax(mp, d);
             }
         };
@@ -436,23 +448,15 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
         for (; t + 3 <= cnt; t += 4) {
             float2 pj[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                int j = i + t + u;
-                if (j >= n) j -= n;
-                pj[u] = pos[j];
-            }
+            for (int u = 0; u < 4; ++u) pj[u] = pos[i + t + u];
 #pragma unroll
             for (int u = 0; u < 4; ++u) pair(pj[u]);
         }
-        for (; t <= cnt; ++t) {
-            int j = i + t;
-            if (j >= n) j -= n;
-            pair(pos[j]);
-        }
-        const double rho = sqrt(__dadd_rn(__dmul_rn(xi, xi), __dmul_rn(yi, yi)));
-        const double d0 = __dsub_rn(__dadd_rn(rho, 1.0), Rb);
+        for (; t <= cnt; ++t) pair(pos[i + t]);
+        const double rho = sqrt(xi * xi + yi * yi);
+        const double d0 = (rho + 1.0) - Rb;
         if (d0 > 0.0) {
-            sc = __dadd_rn(sc, __dmul_rn(d0, d0));
+            sc = sc + d0 * d0;
             mc = fmax(mc, d0);
         }
         if (!(isfinite(xi) && isfinite(yi))) sc = __builtin_nan("");
