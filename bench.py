@@ -30,6 +30,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
 FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32, TFLOP/s
+FP64_PEAK_TFLOPS = 78.6          # MI355X vector FP64, TFLOP/s
 BF16_PEAK_TFLOPS = 2500.0        # MI355X dense BF16 matrix cores, TFLOP/s
 MLP_FLOPS_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)   # multiply-adds of the 8-64-64-1 network
 COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
@@ -418,7 +419,15 @@ def main():
         "iters_mean": float(res["iters"].mean()), "evals_mean": float(res["evals"].mean()),
         "E64_final_mean": float(e64.cpu().numpy().mean()),
         "roofline": roof,
+        # the FP64 verify of the same step: 5 FP64 flops per pair distance
+        # (two differences, two squares, a sum) over all n(n-1)/2 pairs
+        "roofline_verify": {
+            "kernel": "verify_kernel", "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+            "per_launch_flops": 5.0 * a.batch * N_CIRCLES * (N_CIRCLES - 1) / 2,
+            "avg_launch_ms": float(np.mean(ver_ms)),
+            "achieved": 5.0 * a.batch * N_CIRCLES * (N_CIRCLES - 1) / 2 / (float(np.mean(ver_ms)) / 1e3) / 1e12},
     }
+    line["roofline_verify"]["frac"] = line["roofline_verify"]["achieved"] / FP64_PEAK_TFLOPS
     if main_tune is not None:
         line["autotune"] = {"chosen": main_tune["best"], "sample_instances": 64,
                             "table": main_tune["table"]}
