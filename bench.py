@@ -406,7 +406,8 @@ def main():
         "metric": "L-BFGS descents/sec and pair-evals/sec at n=1000, batched FP32 vs plain, to E<1e-20",
         "value": value, "unit": "descents/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 (f64 verify and near-zero line search)",
+        "vs_baseline": None, "dtype": "f32",
+        "dtype_note": "FP64 in the verify and in the sufficient-decrease test near E = 0",
         "data": "synthetic",
         "config": {"workload": f"{a.batch} random starts, n={N_CIRCLES}, R={R_C2}, m=10, "
                                f"max_iter={a.max_iter}",
