@@ -210,7 +210,7 @@ def parse():
                     help="main step with the autotuner's list cutoff / skin (default 2.3 / 0.15: "
                          "the tuner's early-iteration cost does not predict the tail-bound step)")
     ap.add_argument("--kbatch-ks", default="1,2,3,5,7,10,15", help="batch counts of the study")
-    ap.add_argument("--kbatch-dense-ks", default="1,2,5,10", help="batch counts, dense matrices")
+    ap.add_argument("--kbatch-dense-ks", default="1,2,5,6,10", help="batch counts, dense matrices")
     ap.add_argument("--kbatch-dense-instances", type=int, default=256,
                     help="random starts of the dense-matrix study (0: skip)")
     ap.add_argument("--kbatch-instances", type=int, default=512,
