@@ -463,6 +463,27 @@ def main():
                   f"{abl[f'{tau:g}']['feasible_fraction']:.3f}", file=sys.stderr, flush=True)
         line["tau64_ablation"] = {"workload": "the main step's 256 starts, one launch per tau64",
                                   "by_tau64": abl}
+        # the contact margin: the descent works on circles of radius 1 + mu;
+        # feasibility is decided for unit circles in FP64
+        mab = {}
+        for mu in (0.0, 1e-5, 1e-4, 1e-3):
+            pt = replace(params, contact_margin=mu).c()
+            xt_.copy_(xy0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            P.pecc_lbfgs_descend(d, xt_, pt, outt, ws)
+            e1.record(stream)
+            P.pecc_verify(d, xt_, 1e-20, e64t, None, None, feast)
+            torch.cuda.synchronize()
+            rt = P.results(outt)
+            mab[f"{mu:g}"] = {
+                "kernel_ms": e0.elapsed_time(e1), "feasible_fraction": float(feast.float().mean().item()),
+                "iters_mean": float(rt["iters"].mean()),
+                "status_counts": {P.STATUS[v]: int((rt["status"] == v).sum()) for v in np.unique(rt["status"])}}
+            print(f"[bench] contact margin {mu:g}: {mab[f'{mu:g}']['kernel_ms']:.1f} ms, feasible "
+                  f"{mab[f'{mu:g}']['feasible_fraction']:.3f}", file=sys.stderr, flush=True)
+        line["contact_margin_ablation"] = {"workload": "the main step's 256 starts, one launch per margin",
+                                           "by_margin": mab}
 
     # ---- container adjustment (Alg. 2) of the 256 descended layouts --------
     if not a.no_adjust:
