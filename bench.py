@@ -38,7 +38,7 @@ COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the scales
 # measured on the 1 GiB copy): profiles/energy_grad_kernel_traffic_65536x1000.md.
 # Valid for the kernel as profiled; None for other batch sizes.
-SWEEP_TRAFFIC_BYTES_65536 = 2.5754e9
+SWEEP_TRAFFIC_BYTES_65536 = None
 # HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
 # (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
 DESCENT_TRAFFIC_BYTES_256 = 4.7e6
@@ -181,14 +181,15 @@ def kbatch_study(P, a, dev, stream):
             "whole_instance_descent_ms": e0.elapsed_time(e1)}
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--max-iter", type=int, default=5000)
-    ap.add_argument("--plain-sample", type=int, default=8, help="instances timed one call each")
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="instances timed one call each (0: every instance of the batch)")
     ap.add_argument("--sweep-batch", type=int, default=65536, help="instances in the HBM sweep test")
     ap.add_argument("--sweep-reps", type=int, default=20)
     ap.add_argument("--pipeline-streams", type=int, default=4,
@@ -219,7 +220,9 @@ def parse():
     ap.add_argument("--lp-restarts", type=int, default=20000, help="restarts of training data")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle descents (0: the whole batch)")
     ap.add_argument("--cpu-cores", type=int, default=0, help="oracle processes (0: host cores, max 16)")
-    return ap.parse_args()
+    ap.add_argument("--sections-out", default=os.path.join("gpurun_out", "bench_sections.json"),
+                    help="file that receives every section of the run as JSON ('' : none)")
+    return ap.parse_args(argv)
 
 
 def descent_params(P, max_iter):
@@ -421,7 +424,7 @@ def main():
         "status_counts": status_counts,
         "iters_mean": float(res["iters"].mean()), "evals_mean": float(res["evals"].mean()),
         "E64_final_mean": float(e64.cpu().numpy().mean()),
-        "roofline": roof,
+        "roofline_descent": roof,
         # the FP64 verify of the same step: 5 FP64 flops per pair distance
         # (two differences, two squares, a sum) over all n(n-1)/2 pairs
         "roofline_verify": {
@@ -515,7 +518,7 @@ def main():
 
     # ---- plain single-instance path (one call per instance, no graph) ------
     if not a.no_plain:
-        k = min(a.plain_sample, a.batch)
+        k = min(a.plain_sample or a.batch, a.batch)
         subs = []
         for b in range(k):
             one = synth.pack([inst.instance(b)], [inst.R[b]])
@@ -534,10 +537,21 @@ def main():
             torch.cuda.synchronize()
         plain_wall = time.perf_counter() - t0
         plain_rate = k / plain_wall
+        # the plain calls descend the same starts as the batched step: every
+        # final layout must equal the batched one bit for bit
+        xb_all = xy.view(-1, 2)
+        same = all(torch.equal(xw.view(-1, 2), xb_all[int(inst.offset[b]):int(inst.offset[b + 1])])
+                   for b, (_, _, xw, _, _) in enumerate(subs))
+        plain_iters = np.array([int(P.results(ob)["iters"][0]) for *_, ob in subs])
         line["plain_descents_per_s"] = plain_rate
         line["batched_over_plain"] = value / plain_rate
-        line["plain_sample"] = k
-        print(f"[bench] plain: {k} descents in {plain_wall:.3f} s", file=sys.stderr, flush=True)
+        line["plain_instances"] = k
+        line["plain_iters_mean"] = float(plain_iters.mean())
+        line["plain_results_equal_batched"] = bool(same)
+        print(f"[bench] plain: {k} descents in {plain_wall:.3f} s (iterations mean "
+              f"{plain_iters.mean():.0f} vs the batch's {res['iters'][:k].mean():.0f}); layouts equal "
+              f"to the batched step's: {same}", file=sys.stderr, flush=True)
+        del subs
 
     # ---- batched restarts: 256 converged packings, 5% relocated ------------
     if not a.no_restarts:
@@ -591,7 +605,7 @@ def main():
                          "sample_instances": tune["instances"], "table": tune["table"]}}
         if not a.no_plain:
             # plain path on a sample of the restarts: one call per instance, no graph
-            kp = min(a.plain_sample, dr.B)
+            kp = min(a.plain_sample or dr.B, dr.B)
             pl = []
             for b in range(kp):
                 one = synth.pack([rs.instance(b)], [rs.R[b]])
@@ -611,7 +625,7 @@ def main():
             prate = kp / (time.perf_counter() - t0)
             line["restarts"]["plain_descents_per_s"] = prate
             line["restarts"]["batched_over_plain"] = line["restarts"]["descents_per_s"] / prate
-            line["restarts"]["plain_sample"] = kp
+            line["restarts"]["plain_instances"] = kp
         print(f"[bench] restarts: {rms:.2f} ms/step", file=sys.stderr, flush=True)
 
     # ---- geometric batch descent: 64 x n=1000, R=34.4, 4 x 4 blocks -------
@@ -652,6 +666,10 @@ def main():
             ent = {"descents_per_s": dg.B / (np.mean(ts) / 1e3), "kernel_ms": float(np.mean(ts)),
                    "feasible_fraction": float(gf.cpu().numpy().mean()),
                    "outer_iters_mean": float(gr["iters"].mean()),
+                   # trials that moved a batch circle beyond the skin (swept
+                   # over the cell grid: Alg. 1 does not limit the step)
+                   "cell_evals_mean": float(gr["cell_evals"].mean()),
+                   "evals_mean": float(gr["evals"].mean()),
                    "status_counts": {P.STATUS[s]: int((gr["status"] == s).sum()) for s in np.unique(gr["status"])},
                    "E64_median": float(np.median(e64))}
             if margin == 0.0:
@@ -825,21 +843,21 @@ def main():
         c3 = synth.C3(256)
         dc3 = P.DeviceInstances.from_host(c3.offset, c3.R)
         xc3 = torch.from_numpy(c3.xy.reshape(-1)).to(dev)
-        rc3, cc3 = P.build_neighbors(dc3, xc3, 2.3, 0.0, True)
+        rc3, cc3 = P.build_neighbors(dc3, xc3, 2.3, 0.0, P.LIST_LOCAL16)
         Ec3 = torch.empty(dc3.B, dtype=torch.float32, device=dev)
         gc3 = torch.empty_like(xc3)
         for _ in range(5):
-            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), 1.0, Ec3, gc3)
+            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), P.LIST_LOCAL16, 1.0, Ec3, gc3)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(100):
-            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), 1.0, Ec3, gc3)
+            P.pecc_energy_grad(dc3, xc3, rc3, cc3, cc3.numel(), P.LIST_LOCAL16, 1.0, Ec3, gc3)
         e1.record(stream)
         torch.cuda.synchronize()
         t3 = e0.elapsed_time(e1) / 1e3 / 100
         tn3 = dc3.total_n
-        b3 = 8 * tn3 + 8 * tn3 + 4 * (tn3 + dc3.B) + 4 * cc3.numel() + 4 * dc3.B
+        b3 = 8 * tn3 + 8 * tn3 + 4 * (tn3 + dc3.B) + 2 * cc3.numel() + 4 * dc3.B
         line["sweep_c3_effective"] = {
             "kernel": "energy_grad_kernel", "instances": dc3.B, "circles": tn3,
             "per_launch_bytes": b3, "avg_launch_ms": t3 * 1e3,
@@ -851,21 +869,46 @@ def main():
         big = synth.pack([inst.instance(b) for b in range(a.batch)] * reps, list(inst.R) * reps)
         dbig = P.DeviceInstances.from_host(big.offset, big.R)
         xb = torch.from_numpy(big.xy.reshape(-1)).to(dev)
-        row, col = P.build_neighbors(dbig, xb, 2.3, 0.0, True)
+        # the compact list: uint16 instance-local indices, both orientations
+        # (2 bytes per entry, 4 per listed pair)
+        row, col = P.build_neighbors(dbig, xb, 2.3, 0.0, P.LIST_LOCAL16)
         E = torch.empty(dbig.B, dtype=torch.float32, device=dev)
         g = torch.empty_like(xb)
-        for _ in range(5):      # first touches of the fresh output buffers are slower
-            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), 1.0, E, g)
+        # first touches of the fresh output buffers are slower, and the clocks
+        # take some tens of launches to settle
+        for _ in range(40):
+            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), P.LIST_LOCAL16, 1.0, E, g)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(a.sweep_reps):
-            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), 1.0, E, g)
+            P.pecc_energy_grad(dbig, xb, row, col, col.numel(), P.LIST_LOCAL16, 1.0, E, g)
         e1.record(stream)
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) / 1e3 / a.sweep_reps
         tn = dbig.total_n
-        bytes_alg = 8 * tn + 8 * tn + 4 * (tn + dbig.B) + 4 * col.numel() + 4 * dbig.B
+        npairs = col.numel() // 2
+        # per instance 8n (positions) + 8n (gradient) + 4(n+1) (row) + 4P
+        # (P listed pairs) + 4 (E)
+        bytes_alg = 8 * tn + 8 * tn + 4 * (tn + dbig.B) + 4 * npairs + 4 * dbig.B
+        # the other list forms at the same shape, for comparison
+        forms = {}
+        for fname, form in (("int32_each_pair_once", P.LIST_HALF), ("int32_both_orientations", P.LIST_FULL)):
+            rf_, cf_ = P.build_neighbors(dbig, xb, 2.3, 0.0, form)
+            for _ in range(3):
+                P.pecc_energy_grad(dbig, xb, rf_, cf_, cf_.numel(), form, 1.0, E, g)
+            e0.record(stream)
+            for _ in range(5):
+                P.pecc_energy_grad(dbig, xb, rf_, cf_, cf_.numel(), form, 1.0, E, g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tf = e0.elapsed_time(e1) / 1e3 / 5
+            bf = 16 * tn + 4 * (tn + dbig.B) + 4 * cf_.numel() + 4 * dbig.B
+            forms[fname] = {"avg_launch_ms": tf * 1e3, "list_bytes_per_launch": bf,
+                            "GBs_on_these_bytes": bf / tf / 1e9,
+                            "GBs_on_4P_bytes": bytes_alg / tf / 1e9}
+            del rf_, cf_
+        print(f"[bench] sweep list forms: {forms}", file=sys.stderr, flush=True)
         gbs = bytes_alg / t / 1e9
         # plain device copy of a known size: measured copy bandwidth, and the
         # reference dispatch that scales the profiler's byte counters
@@ -886,8 +929,9 @@ def main():
             "traffic": SWEEP_TRAFFIC_BYTES_65536 if dbig.B == 65536 else None,
             "copy_GBs_measured": copy_gbs,
             "per_launch_bytes": bytes_alg, "avg_launch_ms": t * 1e3,
-            "instances": dbig.B, "listed_pairs": int(col.numel() // 2),
-            "pair_evals_per_s": (col.numel() // 2) / t}
+            "instances": dbig.B, "listed_pairs": int(npairs),
+            "list_form": "uint16 instance-local indices, both orientations",
+            "pair_evals_per_s": npairs / t, "other_list_forms": forms}
         print(f"[bench] sweep: {dbig.B} instances, {bytes_alg / 1e9:.2f} GB in {t * 1e3:.3f} ms "
               f"= {gbs:.0f} GB/s", file=sys.stderr, flush=True)
         del big, dbig, xb, row, col, E, g
@@ -937,7 +981,45 @@ def main():
         line["cpu_baseline"] = run_cpu_baseline(inst, a.max_iter, sample, cores,
                                                 gpu_pairs_per_eval=pair_evals / max(1, int(res["evals"].sum())))
 
-    print(json.dumps(line), flush=True)
+    if a.sections_out:
+        os.makedirs(os.path.dirname(os.path.abspath(a.sections_out)), exist_ok=True)
+        with open(a.sections_out, "w") as fh:
+            json.dump(line, fh, indent=1)
+        print(f"[bench] every section written to {a.sections_out}", file=sys.stderr, flush=True)
+    print(json.dumps(compact_line(line, a.sections_out)), flush=True)
+
+
+def _pick(d, keys):
+    return {k: d[k] for k in keys if k in d}
+
+
+def compact_line(line, sections_file=None):
+    """The one JSON line of the run: the headline metric, the plain path,
+    the sweep's HBM roofline (with the descent kernel's ALU fraction beside
+    it) and the CPU baseline.  Every other section goes to the sections
+    file; this line stays well under 2 KB."""
+    out = _pick(line, ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                       "higher_is_better", "scaling", "vs_baseline", "dtype", "data"))
+    out["config"] = _pick(line.get("config", {}), ("workload", "instances", "n", "R"))
+    out.update(_pick(line, ("pair_evals_per_s", "feasible_fraction", "descent_ms_events_median",
+                            "plain_descents_per_s", "batched_over_plain", "plain_instances")))
+    desc = line.get("roofline_descent")
+    desc_c = _pick(desc, ("kernel", "bound", "achieved", "peak", "unit", "frac", "avg_launch_ms",
+                          "busy_cu_share")) if desc else None
+    sweep = line.get("roofline_sweep")
+    if sweep:
+        roof = _pick(sweep, ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                             "per_launch_bytes", "avg_launch_ms", "instances", "listed_pairs"))
+        roof["descent"] = desc_c
+        out["roofline"] = roof
+    elif desc_c:
+        out["roofline"] = desc_c
+    cpu = line.get("cpu_baseline")
+    if cpu:
+        out["cpu_baseline"] = _pick(cpu, ("value", "unit", "cores", "kind", "sample"))
+    if sections_file:
+        out["sections_file"] = sections_file
+    return out
 
 
 if __name__ == "__main__":

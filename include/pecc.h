@@ -82,43 +82,64 @@ const char *pecc_version(void);
  *     neighbor  <=>  dx*dx + dy*dy < cutoff*cutoff     (cutoff as double)
  * so the pair set is a deterministic function of the FP32 input.
  *
- * Output is CSR over global circle indices: the list of circle i is
- * col[row[i]] .. col[row[i+1]-1], ascending.  full = 0 keeps only j > i
- * (each pair once); full = 1 keeps both orientations (pecc_energy_grad
- * wants this form).  row has total_n + 1 entries, row[0] = 0.
+ * Output is CSR: the list of circle i is col[row[i]] .. col[row[i+1]-1],
+ * ascending.  row has total_n + 1 entries (int32), row[0] = 0.  format:
+ *   PECC_LIST_HALF     int32 global circle indices, only j > i (each pair
+ *                      once);
+ *   PECC_LIST_FULL     int32 global circle indices, both orientations;
+ *   PECC_LIST_LOCAL16  uint16 instance-local indices (j - offset[b]), both
+ *                      orientations: 2 bytes per entry, so the list costs
+ *                      as many bytes as the half list in int32 (col must
+ *                      be 2-byte aligned).
+ * (The values 0 and 1 are the former full = 0 / full = 1.)
  * *num_pairs (device, one int64) receives the number of entries required.
  * If it exceeds capacity, row is still complete, nothing is written at or
  * beyond col[capacity], rows ending within the capacity are complete and
  * the row crossing it holds only part of its entries: re-run with a larger
  * col.
  * cell_size <= 0 selects cutoff; otherwise it must be >= cutoff.
+ * Errors: PECC_ERR_INVALID for an unknown format or a misaligned col.
  * Workspace: pecc_build_neighbors_workspace_size().
  * ------------------------------------------------------------------------ */
+#define PECC_LIST_HALF    0
+#define PECC_LIST_FULL    1
+#define PECC_LIST_LOCAL16 2
 int pecc_build_neighbors_workspace_size(const pecc_instances *inst, size_t *bytes /*host*/);
 int pecc_build_neighbors(const pecc_instances *inst, const float *xy,
-                         double cutoff, float cell_size, int32_t full,
-                         int32_t *row, int32_t *col, int64_t capacity,
+                         double cutoff, float cell_size, int32_t format,
+                         int32_t *row, void *col, int64_t capacity,
                          int64_t *num_pairs, void *workspace, size_t workspace_bytes,
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Energy and gradient (Def. 3.1, Def. 3.2; E = sum_{i<j} d_ij^2 +
- * sum_i d_i0^2) in FP32 over a FULL neighbor list from
- * pecc_build_neighbors(full = 1).  Pairs outside the list contribute
+ * sum_i d_i0^2) in FP32 over a neighbor list from pecc_build_neighbors in
+ * the given format (PECC_LIST_*).  Pairs outside the list contribute
  * nothing, so the list must contain every overlapping pair (any list built
  * with cutoff >= 2*rad at positions each circle has since moved less than
- * (cutoff - 2*rad)/2 from qualifies).
+ * (cutoff - 2*rad)/2 from qualifies).  Entries j <= i of a PECC_LIST_HALF
+ * row are skipped, so a list with both orientations passed as HALF holds
+ * the same pairs.  Each circle's gradient is accumulated by one thread in
+ * ascending order of the other circle (no atomics), so the result is
+ * bitwise reproducible; the two forms with both orientations give the same
+ * bits, the half form the same values to FP32 rounding.
+ *   PECC_LIST_LOCAL16  the compact form (2 bytes per entry, 4 bytes per
+ *                      pair): the sweep of choice;
+ *   PECC_LIST_FULL     the same sweep over int32 global indices;
+ *   PECC_LIST_HALF     each pair's term formed once and the partners below
+ *                      a circle gathered on chip (a counting sort of the
+ *                      list by the higher circle).
  * rad is the circle radius used by the energy (1 for unit circles).
  * col_len is the number of entries col holds: list entries at or beyond it
- * are never read, and an instance whose row range leaves [0, col_len) gets
- * energy NaN.
- * energy: device [B]; grad: device [2*total_n] or NULL.  Each circle's
- * gradient is accumulated by one thread in list order (no atomics), so the
- * result is bitwise reproducible.
+ * are never read.  An instance whose row range leaves [0, col_len) gets
+ * energy NaN, and so does, with PECC_LIST_HALF, one whose row offsets
+ * decrease (its gradient is then not written).
+ * energy: device [B]; grad: device [2*total_n] or NULL.
+ * Errors: PECC_ERR_INVALID for an unknown format or a misaligned col.
  * ------------------------------------------------------------------------ */
 int pecc_energy_grad(const pecc_instances *inst, const float *xy,
-                     const int32_t *row, const int32_t *col, int64_t col_len, float rad,
-                     float *energy, float *grad, hipStream_t stream);
+                     const int32_t *row, const void *col, int64_t col_len, int32_t format,
+                     float rad, float *energy, float *grad, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * L-BFGS descent of E at fixed R (Alg. 1 with the limited-memory reading of
@@ -161,6 +182,11 @@ typedef struct pecc_descent_result {
     float   gnorm;          /* final ||g||_2 (FP32)                             */
     double  E64;            /* final FP64 energy of unit circles, or -1 if the
                                descent never entered the FP64 regime           */
+    int32_t cell_evals;     /* evaluations swept over the cell grid instead of
+                               the neighbor lists: a list overflowed, or (the
+                               geometric batch descent) a trial moved a circle
+                               of its batch beyond the skin                    */
+    int32_t reserved;       /* 0                                               */
 } pecc_descent_result;
 
 /* Fill *p with the defaults listed above. (host) */

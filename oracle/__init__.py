@@ -268,12 +268,12 @@ def verify(xy32, R: float, tol: float = 1e-20):
 
 class _GboParams(C.Structure):
     _fields_ = [("blocks", C.c_int32), ("max_outer", C.c_int32), ("jacobi", C.c_int32),
-                ("pad", C.c_int32), ("skin_half", C.c_double)]
+                ("pad", C.c_int32)]
 
 
 class _GboResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("visits", C.c_int32),
-                ("evals", C.c_int32), ("stalled_visits", C.c_int32), ("ref_resets", C.c_int32),
+                ("evals", C.c_int32), ("stalled_visits", C.c_int32), ("pad", C.c_int32),
                 ("E", C.c_double), ("gsum", C.c_double)]
 
 
@@ -289,13 +289,14 @@ def gbo_batches(xy, R: float, blocks: int):
 
 
 def gbo_descend(xy, R: float, params: DescentParams | None = None, blocks: int = 4,
-                max_outer: int = 5000, jacobi: bool = True, skin_half: float = 0.15,
-                trace: bool = False):
-    """Geometric batch descent in FP64.  Returns (xy_final, result, trace)."""
+                max_outer: int = 5000, jacobi: bool = True, trace: bool = False):
+    """Geometric batch descent (Alg. 1 over grid blocks, Eq. 7) in FP64 over
+    all pairs; no step is limited but by the line search.  Returns
+    (xy_final, result, trace)."""
     P = params or DescentParams()
     x, px = _d(np.array(np.asarray(xy).reshape(-1, 2), dtype=np.float64, copy=True))
     cp = _Params(**asdict(P))
-    gp = _GboParams(int(blocks), int(max_outer), 1 if jacobi else 0, 0, float(skin_half))
+    gp = _GboParams(int(blocks), int(max_outer), 1 if jacobi else 0, 0)
     cr = _GboResult()
     tr = np.zeros(max_outer + 1, dtype=np.float64) if trace else None
     rc = lib().oracle_gbo_descend(x.shape[0], px, float(R), C.byref(cp), C.byref(gp), C.byref(cr),
@@ -303,8 +304,7 @@ def gbo_descend(xy, R: float, params: DescentParams | None = None, blocks: int =
     if rc != 0:
         raise RuntimeError(f"oracle_gbo_descend failed ({rc})")
     res = {"status": STATUS[cr.status], "outer": cr.outer, "visits": cr.visits,
-           "evals": cr.evals, "stalled_visits": cr.stalled_visits,
-           "ref_resets": cr.ref_resets, "E": cr.E, "gsum": cr.gsum}
+           "evals": cr.evals, "stalled_visits": cr.stalled_visits, "E": cr.E, "gsum": cr.gsum}
     if trace:
         tr = tr[:cr.outer + 1]
     return x, res, tr

@@ -506,12 +506,9 @@ int oracle_verify(int n, const float *xy, double R, double tol, double *out)
 /* A visit is one quasi-Newton iteration on E(x_p) (Eq. 7) with the other   */
 /* circles fixed: gradient, direction from the batch's own (s, y) history,  */
 /* backtracking sufficient decrease, curvature pair under the same fixed     */
-/* environment.  skin_half > 0 caps every trial: a step that would move a    */
-/* circle more than skin_half away from its reference position is halved     */
-/* (counted as a halving); after each colour the references are reset to     */
-/* the current positions once some circle has moved more than skin_half/2   */
-/* (the GPU rebuilds its neighbor lists at that point).  A visit whose line  */
-/* search fails leaves the batch unchanged.                                  */
+/* environment.  The pairs are all pairs (brute force), so no step length   */
+/* is limited by anything but the line search.  A visit whose line search   */
+/* fails leaves the batch unchanged.                                         */
 /*                                                                           */
 /* Outer iteration of Alg. 1: stop tests at its top: non-finite              */
 /* E, E < e_feasible, sum over batches of ||g(x_p)||_2 of the previous outer */
@@ -523,7 +520,6 @@ typedef struct {
     int32_t max_outer;
     int32_t jacobi;
     int32_t pad;
-    double skin_half;
 } oracle_gbo_params;
 
 typedef struct {
@@ -532,7 +528,7 @@ typedef struct {
     int32_t visits;
     int32_t evals;
     int32_t stalled_visits;
-    int32_t ref_resets;
+    int32_t pad;
     double E;
     double gsum;
 } oracle_gbo_result;
@@ -568,7 +564,6 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
     double *snap = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
     double *env = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
     double *nx = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
-    double *xref = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
     double *g = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
     double *gt = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
     double *bg = malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
@@ -580,7 +575,7 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
     double *ehist = calloc(W + 1, sizeof(double));
     int rc = 0;
     if (!batch_of || !colour_of || !mask || !cnt || !start || !member || !kh || !Sh || !Yh ||
-        !snap || !env || !nx || !xref || !g || !gt || !bg || !bp || !bs || !by || !bx0 || !ehist) {
+        !snap || !env || !nx || !g || !gt || !bg || !bp || !bs || !by || !bx0 || !ehist) {
         rc = -1;
         goto done;
     }
@@ -599,11 +594,9 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
         Yh[p] = calloc((size_t)m * (dim > 0 ? dim : 1), sizeof(double));
         if (!Sh[p] || !Yh[p]) { rc = -1; goto done; }
     }
-    memcpy(xref, xy, sizeof(double) * 2 * n);
-    int visits = 0, evals = 0, stalled = 0, resets = 0, t = 0, status = OR_RUNNING;
+    int visits = 0, evals = 0, stalled = 0, t = 0, status = OR_RUNNING;
     double E = oracle_energy_grad(n, xy, R, P->rad, NULL, NULL, NULL);
     double gsum_prev = -1.0, gsum = 0.0;
-    const double cap2 = G->skin_half * G->skin_half;
     for (t = 0;; ++t) {
         if (trace) trace[t] = E;
         if (!isfinite(E)) { status = OR_NONFINITE; break; }
@@ -657,18 +650,10 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
                 int accepted = 0;
                 double Et = 0.0;
                 for (int h = 0; h <= P->max_halvings; ++h) {
-                    int capped = 0;
                     for (int q = 0; q < np; ++q) {
-                        const double tx = bx0[2 * q] + alpha * bp[2 * q];
-                        const double ty = bx0[2 * q + 1] + alpha * bp[2 * q + 1];
-                        env[2 * mem[q]] = tx;
-                        env[2 * mem[q] + 1] = ty;
-                        if (G->skin_half > 0.0) {
-                            const double dx = tx - xref[2 * mem[q]], dy = ty - xref[2 * mem[q] + 1];
-                            if (dx * dx + dy * dy > cap2) capped = 1;
-                        }
+                        env[2 * mem[q]] = bx0[2 * q] + alpha * bp[2 * q];
+                        env[2 * mem[q] + 1] = bx0[2 * q + 1] + alpha * bp[2 * q + 1];
                     }
-                    if (capped) { alpha *= 0.5; continue; }
                     Et = oracle_batch_energy_grad(n, env, R, P->rad, mask, gt);
                     ++evals;
                     if (Et <= Ep + P->c1 * alpha * gp) { accepted = 1; break; }
@@ -706,15 +691,6 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
                 if (!G->jacobi) memcpy(xy, nx, sizeof(double) * 2 * n);
             }
             memcpy(xy, nx, sizeof(double) * 2 * n);
-            if (G->skin_half > 0.0) {
-                double mx = 0.0;
-                for (int i = 0; i < n; ++i) {
-                    const double dx = xy[2 * i] - xref[2 * i], dy = xy[2 * i + 1] - xref[2 * i + 1];
-                    const double d2 = dx * dx + dy * dy;
-                    if (d2 > mx) mx = d2;
-                }
-                if (mx > 0.25 * cap2) { memcpy(xref, xy, sizeof(double) * 2 * n); ++resets; }
-            }
         }
         gsum_prev = gsum;
         E = oracle_energy_grad(n, xy, R, P->rad, NULL, NULL, NULL);
@@ -724,14 +700,13 @@ int oracle_gbo_descend(int n, double *xy, double R, const oracle_params *P,
     res->visits = visits;
     res->evals = evals;
     res->stalled_visits = stalled;
-    res->ref_resets = resets;
     res->E = E;
     res->gsum = gsum_prev;
 done:
     if (Sh) for (int p = 0; p < nb; ++p) free(Sh[p]);
     if (Yh) for (int p = 0; p < nb; ++p) free(Yh[p]);
     free(Sh); free(Yh); free(batch_of); free(colour_of); free(mask); free(cnt); free(start);
-    free(member); free(kh); free(snap); free(env); free(nx); free(xref); free(g); free(gt);
+    free(member); free(kh); free(snap); free(env); free(nx); free(g); free(gt);
     free(bg); free(bp); free(bs); free(by); free(bx0); free(ehist);
     return rc;
 }

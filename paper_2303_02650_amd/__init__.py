@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libpecc.so")
 
 PECC_MAX_N = 1024
 PECC_MAX_M = 10
+# neighbor-list forms (PECC_LIST_*)
+LIST_HALF, LIST_FULL, LIST_LOCAL16 = 0, 1, 2
 STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED", 4: "STALLED",
           5: "MAX_ITER", 6: "NONFINITE", 7: "BAD_INSTANCE"}
 
@@ -49,8 +51,9 @@ class pecc_descent_params(C.Structure):
 
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("evals", np.int32),
                          ("rebuilds", np.int32), ("pair_evals", np.int64), ("E32", np.float32),
-                         ("gnorm", np.float32), ("E64", np.float64)])
-assert RESULT_DTYPE.itemsize == 40
+                         ("gnorm", np.float32), ("E64", np.float64), ("cell_evals", np.int32),
+                         ("reserved", np.int32)])
+assert RESULT_DTYPE.itemsize == 48
 
 class pecc_adam_params(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
@@ -69,7 +72,8 @@ _sig = {
                                        C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                        C.c_void_p, C.c_size_t, C.c_void_p]),
     "pecc_energy_grad": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_int64, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                   C.c_int64, C.c_int32, C.c_float, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
     "pecc_descent_params_default": (None, [_P(pecc_descent_params)]),
     "pecc_lbfgs_descend_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_lbfgs_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
@@ -178,18 +182,18 @@ def pecc_build_neighbors_workspace_size(inst: DeviceInstances) -> int:
     return b.value
 
 
-def pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, capacity, num_pairs,
+def pecc_build_neighbors(inst, xy, cutoff, cell_size, form, row, col, capacity, num_pairs,
                          workspace, stream=None):
     _check(_lib.pecc_build_neighbors(C.byref(inst.c()), _ptr(xy), float(cutoff), float(cell_size),
-                                     int(full), _ptr(row), _ptr(col), int(capacity),
+                                     int(form), _ptr(row), _ptr(col), int(capacity),
                                      _ptr(num_pairs), _ptr(workspace),
                                      workspace.numel() * workspace.element_size(),
                                      _stream(stream)))
 
 
-def pecc_energy_grad(inst, xy, row, col, col_len, rad, energy, grad, stream=None):
+def pecc_energy_grad(inst, xy, row, col, col_len, form, rad, energy, grad, stream=None):
     _check(_lib.pecc_energy_grad(C.byref(inst.c()), _ptr(xy), _ptr(row), _ptr(col),
-                                 int(col_len), float(rad), _ptr(energy), _ptr(grad),
+                                 int(col_len), int(form), float(rad), _ptr(energy), _ptr(grad),
                                  _stream(stream)))
 
 
@@ -254,27 +258,37 @@ def default_params() -> DescentParams:
 
 
 def build_neighbors(inst: DeviceInstances, xy: torch.Tensor, cutoff: float = 2.3,
-                    cell_size: float = 0.0, full: bool = True, capacity: int | None = None):
-    """Returns (row int32 [total_n+1], col int32 [num_pairs])."""
+                    cell_size: float = 0.0, form: int = LIST_HALF, capacity: int | None = None):
+    """Returns (row int32 [total_n+1], col [num_pairs]) in the list form
+    ``form`` (LIST_HALF / LIST_FULL: int32 global indices; LIST_LOCAL16:
+    instance-local indices held in an int16 tensor, values below 1024;
+    False / True stand for LIST_HALF / LIST_FULL)."""
+    form = int(form)
     dev = xy.device
+    dt = torch.int16 if form == LIST_LOCAL16 else torch.int32
     row = torch.empty(inst.total_n + 1, dtype=torch.int32, device=dev)
     npairs = torch.zeros(1, dtype=torch.int64, device=dev)
     ws = torch.empty(pecc_build_neighbors_workspace_size(inst), dtype=torch.uint8, device=dev)
     cap = capacity if capacity is not None else max(16, 8 * inst.total_n)
-    col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, cap, npairs, ws)
+    col = torch.empty(max(cap, 1), dtype=dt, device=dev)
+    pecc_build_neighbors(inst, xy, cutoff, cell_size, form, row, col, cap, npairs, ws)
     need = int(npairs.item())
     if need > cap:
-        col = torch.empty(need, dtype=torch.int32, device=dev)
-        pecc_build_neighbors(inst, xy, cutoff, cell_size, full, row, col, need, npairs, ws)
+        col = torch.empty(need, dtype=dt, device=dev)
+        pecc_build_neighbors(inst, xy, cutoff, cell_size, form, row, col, need, npairs, ws)
     return row, col[:need]
 
 
 def energy_grad(inst: DeviceInstances, xy: torch.Tensor, row: torch.Tensor, col: torch.Tensor,
-                rad: float = 1.0, want_grad: bool = True):
+                rad: float = 1.0, want_grad: bool = True, form: int | None = None):
+    """E [B] and grad [2 total_n]; the list form defaults to LIST_LOCAL16
+    for an int16 col and LIST_HALF for an int32 one (a list with both
+    orientations read as LIST_HALF gives the same pairs)."""
+    if form is None:
+        form = LIST_LOCAL16 if col.dtype == torch.int16 else LIST_HALF
     E = torch.empty(inst.B, dtype=torch.float32, device=xy.device)
     g = torch.empty_like(xy) if want_grad else None
-    pecc_energy_grad(inst, xy, row, col, col.numel(), rad, E, g)
+    pecc_energy_grad(inst, xy, row, col, col.numel(), form, rad, E, g)
     return E, g
 
 

@@ -60,13 +60,17 @@ int pecc_build_neighbors_workspace_size(const pecc_instances *inst, size_t *byte
 }
 
 int pecc_build_neighbors(const pecc_instances *inst, const float *xy, double cutoff,
-                         float cell_size, int32_t full, int32_t *row, int32_t *col,
+                         float cell_size, int32_t format, int32_t *row, void *col,
                          int64_t capacity, int64_t *num_pairs, void *workspace,
                          size_t workspace_bytes, hipStream_t stream)
 {
     const char *fn = "pecc_build_neighbors";
     int rc = check_inst(inst, fn);
     if (rc) return rc;
+    if (format != PECC_LIST_HALF && format != PECC_LIST_FULL && format != PECC_LIST_LOCAL16)
+        return fail(PECC_ERR_INVALID, "%s: unknown list format %d", fn, format);
+    if (format == PECC_LIST_LOCAL16 && (reinterpret_cast<uintptr_t>(col) & 1))
+        return fail(PECC_ERR_INVALID, "%s: a 16-bit list must be 2-byte aligned", fn);
     if (!(cutoff > 0.0) || !isfinite(cutoff)) return fail(PECC_ERR_INVALID, "%s: cutoff must be > 0", fn);
     if (cell_size > 0.f && (double)cell_size < cutoff)
         return fail(PECC_ERR_INVALID, "%s: cell_size %g < cutoff %g", fn, cell_size, cutoff);
@@ -81,19 +85,23 @@ int pecc_build_neighbors(const pecc_instances *inst, const float *xy, double cut
         return fail(PECC_ERR_WORKSPACE, "%s: workspace needs %zu bytes", fn, need);
     const float h = (float)((cell_size > 0.f ? (double)cell_size : cutoff) * (1.0 + 1e-4));
     return check_hip(pecc::launch_build(inst->offset, inst->R, xy, inst->num_instances,
-                                        inst->total_n, cutoff, h, full ? 1 : 0, row, col,
+                                        inst->total_n, cutoff, h, format, row, col,
                                         capacity, num_pairs, (int64_t *)workspace, stream),
                      fn);
 }
 
 // ---------------------------------------------------------------------------
 int pecc_energy_grad(const pecc_instances *inst, const float *xy, const int32_t *row,
-                     const int32_t *col, int64_t col_len, float rad, float *energy,
-                     float *grad, hipStream_t stream)
+                     const void *col, int64_t col_len, int32_t format, float rad,
+                     float *energy, float *grad, hipStream_t stream)
 {
     const char *fn = "pecc_energy_grad";
     int rc = check_inst(inst, fn);
     if (rc) return rc;
+    if (format != PECC_LIST_HALF && format != PECC_LIST_FULL && format != PECC_LIST_LOCAL16)
+        return fail(PECC_ERR_INVALID, "%s: unknown list format %d", fn, format);
+    if (format == PECC_LIST_LOCAL16 && (reinterpret_cast<uintptr_t>(col) & 1))
+        return fail(PECC_ERR_INVALID, "%s: a 16-bit list must be 2-byte aligned", fn);
     if (!energy) return fail(PECC_ERR_INVALID, "%s: energy is NULL", fn);
     if (!row) return fail(PECC_ERR_INVALID, "%s: row is NULL", fn);
     if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
@@ -101,8 +109,8 @@ int pecc_energy_grad(const pecc_instances *inst, const float *xy, const int32_t 
     if (col_len < 0) return fail(PECC_ERR_INVALID, "%s: col_len < 0", fn);
     if (col_len > 0 && !col) return fail(PECC_ERR_INVALID, "%s: col is NULL", fn);
     return check_hip(pecc::launch_energy_grad(inst->offset, inst->R, xy, inst->num_instances,
-                                              inst->total_n, row, col, col_len, rad, energy,
-                                              grad, stream),
+                                              inst->total_n, row, col, col_len, format, rad,
+                                              energy, grad, stream),
                      fn);
 }
 
@@ -610,7 +618,9 @@ int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
 
 }  // extern "C"
 
-static_assert(sizeof(pecc_descent_result) == 40, "result layout");
+static_assert(sizeof(pecc_descent_result) == 48, "result layout");
 static_assert(sizeof(pecc_descent_params) == 64, "params layout");
 static_assert(PECC_MAX_BATCHES == pecc::kMaxSeqBatches, "batch limit");
+static_assert(PECC_LIST_HALF == pecc::kListHalf && PECC_LIST_FULL == pecc::kListFull &&
+              PECC_LIST_LOCAL16 == pecc::kListLocal16, "list forms");
 static_assert(sizeof(pecc_adam_params) == 16, "adam params layout");

@@ -56,6 +56,7 @@ struct DescentShared {
     int flag[2];
     int over;                      // a circle had more than ELL neighbors
     int work;
+    int cell_evals;                // evaluations over the cell grid (instance)
 };
 
 // Batch descent only: the saved Gram matrix of every batch, batch ids and
@@ -301,12 +302,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         const int off = offset[b], n = offset[b + 1] - off;
         if (!(off >= 0 && n >= 0 && n <= kMaxN && (int64_t)off + n <= total_n)) {
             if (tid == 0) {
-                DescentResultDev r = {};
+                DescentHead r = {};
                 r.status = 7;  // BAD_INSTANCE
                 r.E32 = __builtin_nanf("");
                 r.gnorm = __builtin_nanf("");
                 r.E64 = -1.0;
-                out[b] = r;
+                store_result(out, b, r, 0);
             }
             continue;
         }
@@ -351,12 +352,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             if (__syncthreads_or(bad)) {
                 if (tid == 0) {
-                    DescentResultDev r = {};
+                    DescentHead r = {};
                     r.status = 7;  // BAD_INSTANCE: a batch id out of range
                     r.E32 = __builtin_nanf("");
                     r.gnorm = __builtin_nanf("");
                     r.E64 = -1.0;
-                    out[b] = r;
+                    store_result(out, b, r, 0);
                 }
                 continue;
             }
@@ -402,12 +403,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             __syncthreads();
             if ((int64_t)sq.voff[A.nbat] > A.hstride) {
                 if (tid == 0) {
-                    DescentResultDev r = {};
+                    DescentHead r = {};
                     r.status = 7;  // BAD_INSTANCE: the matrices do not fit the workspace
                     r.E32 = __builtin_nanf("");
                     r.gnorm = __builtin_nanf("");
                     r.E64 = -1.0;
-                    out[b] = r;
+                    store_result(out, b, r, 0);
                 }
                 continue;
             }
@@ -724,7 +725,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         };
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
-        if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; }
+        if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0; }
 
         // container adjustment state (uniform): radius, its gradient and
         // search components, penalty coefficient; hR_v: radius component of
@@ -831,6 +832,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             ++tcount;
             ++evals;
+            // evaluations over the cell grid, counted in LDS (no register
+            // stays live for a number read once at the end)
+            if (overflow && tid == 0) ++sh.cell_evals;
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) pair_mine += inb[c] ? half_mine[c] : 0;
             // ---- pair sweep: energy and gradient of this thread's circles ----
@@ -1279,7 +1283,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         for (int c = 0; c < kCPT; ++c)
             if (act[c]) reinterpret_cast<float2 *>(xy)[off + tid + c * kDB] = x[c];
         if (tid == 0) {
-            DescentResultDev r;
+            DescentHead r;
             r.status = status;
             r.iters = iters_all;
             r.evals = evals;
@@ -1297,7 +1301,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 r.gnorm = gsum_prev;
                 r.E64 = E64t;
             }
-            out[b] = r;
+            store_result(out, b, r, sh.cell_evals);
             if constexpr (ADJ) Rout[b] = Rz;
         }
     }

@@ -17,10 +17,15 @@
 //   * the other circles are seen at their positions from the start of the
 //     colour (the batches of a colour run concurrently); the batch's own
 //     trial positions live in a separate LDS array;
-//   * a trial that would move a circle more than skin_half from the
-//     positions of the last neighbor-list rebuild is halved (the list stays
-//     valid through the whole colour); after a colour the lists are rebuilt
-//     once some circle has moved more than skin_half / 2;
+//   * neighbor lists (cutoff 2 rad + 2 skin) are rebuilt after a colour once
+//     some circle has moved more than skin / 2 from the positions of the
+//     last rebuild, so every circle starts a colour within skin / 2 of them.
+//     A trial that keeps the batch's circles within skin of those positions
+//     is evaluated over the lists; a longer trial (the step of Alg. 1 is not
+//     limited) over the cell grid of the last rebuild for the other circles
+//     (still within skin / 2 of their cells' positions, so the 3 x 3 cells
+//     around the trial position hold every partner closer than 2 rad) and
+//     over all of the batch's own circles;
 //   * per-batch history (a ring of m pairs) and Gram matrix persist between
 //     visits in the caller's workspace (L2-resident per instance).
 // Results are bitwise reproducible: membership, list order and every sum
@@ -104,12 +109,12 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
         const double R64 = Rv64 ? Rv64[b] : (double)R;
         auto bad_instance = [&]() {
             if (tid == 0) {
-                DescentResultDev r = {};
+                DescentHead r = {};
                 r.status = 7;
                 r.E32 = __builtin_nanf("");
                 r.gnorm = __builtin_nanf("");
                 r.E64 = -1.0;
-                out[b] = r;
+                store_result(out, b, r, 0);
             }
         };
         if (!(off >= 0 && n >= 0 && n <= kMaxN && (int64_t)off + n <= total_n)) {
@@ -173,6 +178,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
         }
 
         int rebuilds = 0, evals = 0, status = 0, outer = 0;
+        int cell_mine = 0;      // this wave's evaluations over the cell grid
         int64_t pair_mine = 0;
         bool overflow = false;
         double ehist = 0.0, E64t = -1.0;
@@ -342,7 +348,8 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     float Ep = 0.f;
                     double Ep64 = 0.0;
                     auto evaluate = [&](const float2 (&xt)[kGCPB], const float2 (&sc)[kGCPB],
-                                        float2 (&gt)[kGCPB], float2 (&yc)[kGCPB], double &e64) -> float {
+                                        float2 (&gt)[kGCPB], float2 (&yc)[kGCPB], double &e64,
+                                        bool far) -> float {
 #pragma unroll
                         for (int c = 0; c < kGCPB; ++c)
                             if (act[c]) sh.tpos[ci[c]] = xt[c];
@@ -382,7 +389,18 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                                         pair_term32(q, pj, ce, two_r, four_r2, e, e1, gx, gy);
                                     }
                                 };
-                                if (!overflow) {
+                                if (far) {
+                                    // a circle of the batch left the skin: the other
+                                    // circles from the cell grid, the batch's own from
+                                    // its member list
+                                    for_each_candidate(i, q, grid, sh.cell_start, sh.cell_circ, [&](int j) {
+                                        if (sh.batch_of[j] != p) term(j);
+                                    });
+                                    for (int t = 0; t < np; ++t) {
+                                        const int j = sh.members[m0 + t];
+                                        if (j != i) term(j);
+                                    }
+                                } else if (!overflow) {
                                     const int mc = sh.list_n[i];
                                     for (int t = 0; t < mc; ++t) term(sh.list[t][i]);
                                 } else {
@@ -420,6 +438,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                         if (F64) e = (float)ed;
                         e64 = wave_sum(ed);
                         ++evals;
+                        cell_mine += (far || overflow) ? 1 : 0;
                         pair_mine += pe;
                         return wave_reduce_scatter<kGCPB>(gt, sc, yc, S, Y, e, e1);
                     };
@@ -429,7 +448,9 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
 #pragma unroll
                     for (int c = 0; c < kGCPB; ++c) sc0[c] = make_float2(0.f, 0.f);
                     double e64 = 0.0;
-                    float tot = evaluate(x, sc0, gt, yc, e64);
+                    // (every circle starts a colour within skin / 2 of its list
+                    // position, so the visit's first point is in range of the lists)
+                    float tot = evaluate(x, sc0, gt, yc, e64, false);
                     // slot totals are lane-indexed by lane_slot(); stage them
                     sh.totw[wv][lane_slot(lane)] = tot;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -508,7 +529,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     bool accepted = false, push = false;
                     float2 xt[kGCPB], sc[kGCPB];
                     for (int h = 0; h <= A.max_halvings; ++h) {
-                        bool capped = false;
+                        bool out = false;
 #pragma unroll
                         for (int c = 0; c < kGCPB; ++c) {
                             xt[c] = make_float2(fmaf(alpha, pd[c].x, x[c].x), fmaf(alpha, pd[c].y, x[c].y));
@@ -516,11 +537,11 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                             if (act[c]) {
                                 const float2 rf = sh.xref[ci[c]];
                                 const double dx = (double)xt[c].x - (double)rf.x, dy = (double)xt[c].y - (double)rf.y;
-                                capped |= dx * dx + dy * dy > A.skin2;
+                                out |= dx * dx + dy * dy > A.skin2;
                             }
                         }
-                        if (__builtin_amdgcn_ballot_w64(capped) != 0) { alpha *= 0.5f; continue; }
-                        tot = evaluate(xt, sc, gt, yc, e64);
+                        const bool far = __builtin_amdgcn_ballot_w64(out) != 0;
+                        tot = evaluate(xt, sc, gt, yc, e64, far);
                         sh.totw[wv][lane_slot(lane)] = tot;
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         __builtin_amdgcn_wave_barrier();
@@ -629,8 +650,15 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
             for (int w = 0; w < kGW; ++w) pm += __builtin_bit_cast(unsigned long long, sh.redd[0][w]);
             pair_mine = (int64_t)pm;
         }
+        {
+            __syncthreads();
+            if (lane == 0) sh.scan_tmp[wv] = cell_mine;
+            __syncthreads();
+            cell_mine = 0;
+            for (int w = 0; w < kGW; ++w) cell_mine += sh.scan_tmp[w];
+        }
         if (tid == 0) {
-            DescentResultDev r;
+            DescentHead r;
             r.status = status;
             r.iters = outer;
             r.evals = evals;
@@ -639,7 +667,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
             r.E32 = Ew;
             r.gnorm = gs_all;
             r.E64 = E64t;
-            out[b] = r;
+            store_result(out, b, r, cell_mine);
         }
     }
 }

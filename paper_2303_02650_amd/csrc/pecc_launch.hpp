@@ -5,14 +5,19 @@
 
 namespace pecc {
 
+// Neighbor-list forms (the values of PECC_LIST_*): int32 global indices
+// with each pair once or in both orientations, uint16 instance-local
+// indices in both orientations.
+constexpr int kListHalf = 0, kListFull = 1, kListLocal16 = 2;
+
 hipError_t launch_build(const int32_t *offset, const float *R, const float *xy, int B,
-                        int64_t total_n, double cutoff, float h_req, int full,
-                        int32_t *row, int32_t *col, int64_t capacity, int64_t *num_pairs,
+                        int64_t total_n, double cutoff, float h_req, int format,
+                        int32_t *row, void *col, int64_t capacity, int64_t *num_pairs,
                         int64_t *inst_total, hipStream_t s);
 
 hipError_t launch_energy_grad(const int32_t *offset, const float *R, const float *xy, int B,
-                              int64_t total_n, const int32_t *row, const int32_t *col,
-                              int64_t col_len, float rad, float *energy, float *grad,
+                              int64_t total_n, const int32_t *row, const void *col,
+                              int64_t col_len, int format, float rad, float *energy, float *grad,
                               hipStream_t s);
 
 hipError_t launch_verify(const int32_t *offset, const float *R, const double *R64,

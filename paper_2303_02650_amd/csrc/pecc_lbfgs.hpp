@@ -28,13 +28,32 @@ constexpr int sE = sGG + 6;                                 // trial energy (rad
 constexpr int sE1 = sGG + 7;                                // trial energy of unit circles
 static_assert(sE1 < kWave, "fused reduction must fit one slot per lane");
 
-// Layout-identical mirror of pecc_descent_result.
+// Layout-identical mirror of pecc_descent_result, and its first 40 bytes.
 struct DescentResultDev {
     int32_t status, iters, evals, rebuilds;
     int64_t pair_evals;
     float E32, gnorm;
     double E64;
+    int32_t cell_evals, reserved;
 };
+struct DescentHead {
+    int32_t status, iters, evals, rebuilds;
+    int64_t pair_evals;
+    float E32, gnorm;
+    double E64;
+};
+
+// Writes the result of instance b: the head as one struct, then cell_evals
+// and the reserved word.  (Kernels build the 40-byte head: a 48-byte local
+// struct changes the descent kernel's register allocation -- spills, and in
+// one instantiation a misaligned register pair the compiler rejects.)
+__device__ __forceinline__ void store_result(DescentResultDev *out, int b, const DescentHead &r,
+                                             int cell_evals)
+{
+    char *o = reinterpret_cast<char *>(out) + (size_t)b * sizeof(DescentResultDev);
+    *reinterpret_cast<DescentHead *>(o) = r;
+    *reinterpret_cast<int2 *>(o + sizeof(DescentHead)) = make_int2(cell_evals, 0);
+}
 
 __device__ __forceinline__ float dot2(float2 a, float2 b) { return a.x * b.x + a.y * b.y; }
 

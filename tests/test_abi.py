@@ -105,11 +105,16 @@ def test_build_and_sweep_validation(P):
     # energy/grad
     E = C.c_void_p(0x60)
     f = P._lib.pecc_energy_grad
-    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 0.0, E, None, None) == -1
-    assert f(C.byref(inst), C.c_void_p(0x10), None, C.c_void_p(0x30), 10, 1.0, E, None, None) == -1
-    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), None, 10, 1.0, E, None, None) == -1
-    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), -1, 1.0, E, None, None) == -1
-    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 1.0, None, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 0, 0.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), None, C.c_void_p(0x30), 10, 0, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), None, 10, 0, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), -1, 0, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 0, 1.0, None, None, None) == -1
+    # unknown list form; a 16-bit list at an odd address
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x30), 10, 3, 1.0, E, None, None) == -1
+    assert f(C.byref(inst), C.c_void_p(0x10), C.c_void_p(0x20), C.c_void_p(0x31), 10, 2, 1.0, E, None, None) == -1
+    assert call(full=3) == -1
+    assert call(full=2, col=C.c_void_p(0x31)) == -1
     # verify
     assert P._lib.pecc_verify(C.byref(inst), C.c_void_p(0x10), 1e-20, None, None, None, None, None) == -1
 

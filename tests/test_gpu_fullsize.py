@@ -65,8 +65,9 @@ def test_sweep_full_size_sampled(P):
     big = synth.pack([base.instance(b) for b in range(base.B)] * reps, list(base.R) * reps)
     d = P.DeviceInstances.from_host(big.offset, big.R)
     xy = torch.from_numpy(big.xy.reshape(-1)).cuda()
-    row, col = P.build_neighbors(d, xy, 2.3, 0.0, True)
-    E, g = P.energy_grad(d, xy, row, col)
+    # the benchmark's form: uint16 local indices, both orientations
+    row, col = P.build_neighbors(d, xy, 2.3, 0.0, P.LIST_LOCAL16)
+    E, g = P.energy_grad(d, xy, row, col, form=P.LIST_LOCAL16)
     E = E.cpu().numpy()
     g = g.cpu().numpy().reshape(-1, 2)
     # replicas give the same bits wherever they sit in the launch
@@ -175,11 +176,14 @@ def test_geometric_batches_full_size_sampled(P):
     res = P.results(P.gbo_descend(d, xy, P.DescentParams(max_iter=2, g_tol=0.0, ftol=0.0), blocks=4))
     x = xy.cpu().numpy().reshape(-1, 2)
     assert (res["iters"] == 2).all()
+    # steps longer than the skin happen at these random starts: their trials
+    # are swept over the cell grid, and the oracle (all pairs) follows Alg. 1
+    # without any limit on the step
+    assert (res["cell_evals"] > 0).any()
     for b in (0, 31, 63):
         o0, o1 = inst.offset[b], inst.offset[b + 1]
         x64, r64, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
-                                         oracle.DescentParams(g_tol=0.0), blocks=4, max_outer=2,
-                                         skin_half=0.15)
+                                         oracle.DescentParams(g_tol=0.0), blocks=4, max_outer=2)
         assert np.abs(x[o0:o1] - x64).max() < 1e-4 * max(1.0, np.abs(x64).max())
     prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4)
     runs = []

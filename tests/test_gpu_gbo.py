@@ -1,6 +1,8 @@
 """GPU parity of the geometric batch descent (Alg. 1, Eq. 7) against the
-oracle's batch descent (same partition, colour order, line search and
-displacement cap, FP64)."""
+oracle's batch descent (same partition, colour order and line search; FP64
+over all pairs, no limit on a step).  The GPU sweeps its neighbor lists
+while a trial keeps the batch within the skin and the cell grid otherwise,
+so both cases are compared."""
 import numpy as np
 import pytest
 
@@ -48,12 +50,31 @@ def test_gbo_first_outer_iterations_follow_oracle(P, name, outer, fp64):
         o0, o1 = inst.offset[b], inst.offset[b + 1]
         x64, r64, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
                                          oracle.DescentParams(g_tol=0.0), blocks=blocks,
-                                         max_outer=outer, skin_half=0.15)
+                                         max_outer=outer)
         assert res["iters"][b] == r64["outer"]
         scale = max(1.0, float(np.abs(x64).max()))
         err = np.abs(xg[o0:o1] - x64).max() / scale
         assert err < 5e-5 * outer, (name, b, err)
         # the batch gradient norms of the last outer iteration
+        assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-3)
+
+
+@pytest.mark.parametrize("skin", [0.15, 0.5])
+def test_gbo_off_list_trials_follow_oracle(P, skin):
+    """Random starts of n = 1000: with the 0.15 skin the first visits take
+    steps beyond it (swept over the cell grid); with a 0.5 skin (list cutoff
+    3.0) the lists cover longer steps.  Both follow the oracle."""
+    inst = synth.C4(2)
+    params = P.DescentParams(max_iter=2, g_tol=0.0, ftol=0.0, cutoff=2.0 + 2 * skin, skin_half=skin)
+    xg, res = run(P, inst, params, 4)
+    if skin == 0.15:
+        assert (res["cell_evals"] > 0).all()
+    for b in range(inst.B):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                         oracle.DescentParams(g_tol=0.0), blocks=4, max_outer=2)
+        scale = max(1.0, float(np.abs(x64).max()))
+        assert np.abs(xg[o0:o1] - x64).max() / scale < 1e-4, (skin, b)
         assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-3)
 
 

@@ -184,3 +184,56 @@ def test_concurrent_launches_on_several_streams_match_sequential(P):
     for k, b in enumerate(sets):
         for got, want in zip(b[:2] + b[3:], ref[:2] + ref[3:]):
             assert torch.equal(got, want), k
+
+
+def test_back_to_back_replays_like_the_benchmark(P):
+    """The benchmark's timed loop: K steps, each a replay of the captured
+    reset + descent graph and of the captured verify graph, back to back on
+    one stream with events between them and no host synchronisation.  Every
+    step's results (copied aside on the same stream) equal the eager step's
+    bit for bit."""
+    inst = synth.C2(64)
+    d = P.DeviceInstances.from_host(inst.offset, inst.R)
+    x0 = torch.from_numpy(inst.xy.reshape(-1)).cuda()
+    x = torch.empty_like(x0)
+    prm = P.DescentParams(g_tol=1e-6, ftol=1e-7, ftol_window=20, contact_margin=1e-4,
+                          tau64=1e-5).c()
+    ws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device="cuda")
+    out = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    e64 = torch.empty(d.B, dtype=torch.float64, device="cuda")
+    mp_ = torch.empty_like(e64)
+    mc_ = torch.empty_like(e64)
+    feas = torch.empty(d.B, dtype=torch.int32, device="cuda")
+
+    def descend_once():
+        x.copy_(x0)
+        P.pecc_lbfgs_descend(d, x, prm, out, ws)
+
+    def verify_once():
+        P.pecc_verify(d, x, 1e-20, e64, mp_, mc_, feas)
+
+    descend_once(); verify_once()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (x, out, e64, mp_, mc_, feas)]
+    g_desc, g_ver = capture(descend_once), capture(verify_once)
+    K = 6
+    hist = [[torch.empty_like(t) for t in ref] for _ in range(K)]
+    for t in (x, out, e64, mp_, mc_, feas):
+        t.zero_()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    for k, (e0, e1, e2) in enumerate(evs):
+        e0.record(stream)
+        g_desc.replay()
+        e1.record(stream)
+        g_ver.replay()
+        e2.record(stream)
+        for h, t in zip(hist[k], (x, out, e64, mp_, mc_, feas)):
+            h.copy_(t)
+    torch.cuda.synchronize()
+    for k in range(K):
+        for h, r in zip(hist[k], ref):
+            assert torch.equal(h, r), k
+        assert evs[k][0].elapsed_time(evs[k][1]) > 0.0

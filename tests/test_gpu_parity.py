@@ -49,9 +49,18 @@ def crowded_batch():
     return synth.pack([np.concatenate([core, rest])], [8.0])
 
 
+def tight_batch():
+    # circles far denser than any packing: several thousand listed pairs per
+    # instance (up to ~23k), more than the sweep stages in LDS at once
+    rng = synth.rng_for(12)
+    sizes_R = ((1024, 13.0), (600, 10.0), (300, 30.0))
+    return synth.pack([synth.disk_uniform(n, R, rng) for n, R in sizes_R], [R for _, R in sizes_R])
+
+
 BATCHES = {
     "C1": lambda: synth.C1(),
     "crowded": crowded_batch,
+    "tight": tight_batch,
     "C2": lambda: synth.C2(1),
     "mixed": lambda: mixed_batch(0),
     "C3starts": lambda: synth.C3(24),
@@ -64,13 +73,15 @@ BATCHES = {
 # neighbor lists
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name", list(BATCHES))
-@pytest.mark.parametrize("full", [False, True])
-def test_neighbor_sets_bit_exact(P, name, full):
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_neighbor_sets_bit_exact(P, name, form):
     inst = BATCHES[name]()
     d, xy = to_dev(P, inst)
-    row, col = P.build_neighbors(d, xy, 2.3, 0.0, full)
+    row, col = P.build_neighbors(d, xy, 2.3, 0.0, form)
+    assert col.dtype == (torch.int16 if form == P.LIST_LOCAL16 else torch.int32)
+    full = form != P.LIST_HALF
     row = row.cpu().numpy()
-    col = col.cpu().numpy()
+    col = col.cpu().numpy().astype(np.int64)
     assert row[0] == 0 and row[-1] == len(col)
     for b in range(inst.B):
         o0, o1 = inst.offset[b], inst.offset[b + 1]
@@ -80,8 +91,9 @@ def test_neighbor_sets_bit_exact(P, name, full):
             want.setdefault(i, []).append(j)
             if full:
                 want.setdefault(j, []).append(i)
+        base = 0 if form == P.LIST_LOCAL16 else o0      # local indices need no offset
         for i in range(o1 - o0):
-            got = col[row[o0 + i]:row[o0 + i + 1]] - o0
+            got = col[row[o0 + i]:row[o0 + i + 1]] - base
             w = sorted(want.get(i, []))
             assert got.tolist() == w, (name, b, i)
 
@@ -131,11 +143,12 @@ def test_neighbor_degenerate_layouts(P):
 # energy and gradient
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name", list(BATCHES))
-def test_energy_grad_within_1e5(P, name):
+@pytest.mark.parametrize("form", [0, 2])
+def test_energy_grad_within_1e5(P, name, form):
     inst = BATCHES[name]()
     d, xy = to_dev(P, inst)
-    row, col = P.build_neighbors(d, xy, 2.3, 0.0, True)
-    E, g = P.energy_grad(d, xy, row, col)
+    row, col = P.build_neighbors(d, xy, 2.3, 0.0, form)
+    E, g = P.energy_grad(d, xy, row, col, form=form)
     E = E.cpu().numpy()
     g = g.cpu().numpy().reshape(-1, 2)
     worst = 0.0
@@ -154,10 +167,57 @@ def test_energy_grad_within_1e5(P, name):
     print(f"{name}: worst relative error vs FP64 {worst:.3e}")
 
 
+@pytest.mark.parametrize("name", ["C2", "mixed", "crowded", "tight", "C3restarts"])
+def test_energy_grad_list_forms_agree(P, name):
+    """The three list forms hold the same pairs.  The two with both
+    orientations (int32 global, uint16 local) run the same sweep: the same
+    bits.  The half list forms each pair's term once (the product rounded
+    before it is added, where the other sweep fuses the multiply-add) and
+    adds the same terms in another order: equal to FP32 rounding."""
+    inst = BATCHES[name]()
+    d, xy = to_dev(P, inst)
+    rh, ch = P.build_neighbors(d, xy, 2.3, 0.0, P.LIST_HALF)
+    rf, cf = P.build_neighbors(d, xy, 2.3, 0.0, P.LIST_FULL)
+    rl, cl = P.build_neighbors(d, xy, 2.3, 0.0, P.LIST_LOCAL16)
+    assert cf.numel() == 2 * ch.numel() == cl.numel() and torch.equal(rf, rl)
+    Eh, gh = P.energy_grad(d, xy, rh, ch, form=P.LIST_HALF)
+    Ef, gf = P.energy_grad(d, xy, rf, cf, form=P.LIST_FULL)
+    El, gl = P.energy_grad(d, xy, rl, cl, form=P.LIST_LOCAL16)
+    assert torch.equal(Ef, El) and torch.equal(gf, gl)
+    gh64, gf64 = gh.cpu().numpy().astype(np.float64), gf.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gh64 - gf64) <= 1e-6 * np.linalg.norm(gf64)
+    Eh, Ef = Eh.cpu().numpy().astype(np.float64), Ef.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(Eh - Ef) <= 1e-6 * np.abs(Ef)), (Eh, Ef)
+    # a list with both orientations read as a half list: the same pairs,
+    # the same bits as the half list itself
+    Ex, gx = P.energy_grad(d, xy, rf, cf, form=P.LIST_HALF)
+    assert torch.equal(gx, gh)
+    # the tight batch's lists take several LDS chunks of the half-list sweep
+    # (3024 entries) and overflow the staged segment of the full-list sweep
+    # (6128 entries), which then reads the list from global memory
+    if name == "tight":
+        rows = rh.cpu().numpy()
+        per = [rows[inst.offset[b + 1]] - rows[inst.offset[b]] for b in range(inst.B)]
+        assert max(per) > 3 * 3024 and 2 * max(per) > 6128, per
+
+
+def test_energy_grad_decreasing_rows_give_nan(P):
+    inst = synth.C2(2)
+    d, xy = to_dev(P, inst)
+    row, col = P.build_neighbors(d, xy, 2.3, 0.0, False)
+    bad = row.clone()
+    bad[5], bad[6] = row[6] + 3, row[5]           # row 5 of instance 0 ends before it starts
+    E = torch.empty(2, dtype=torch.float32, device="cuda")
+    g = torch.zeros_like(xy)
+    P.pecc_energy_grad(d, xy, bad, col, col.numel(), P.LIST_HALF, 1.0, E, g)
+    E2, _ = P.energy_grad(d, xy, row, col)
+    assert torch.isnan(E[0]) and E[1] == E2[1]
+
+
 def test_energy_grad_margin_radius(P):
     inst = synth.C2(1)
     d, xy = to_dev(P, inst)
-    row, col = P.build_neighbors(d, xy, 2.3, 0.0, True)
+    row, col = P.build_neighbors(d, xy, 2.3, 0.0, False)
     E, g = P.energy_grad(d, xy, row, col, rad=1.05)
     E64, _, _, g64 = oracle.energy_grad(inst.xy.astype(np.float64), inst.R[0], rad=1.05)
     assert abs(E.item() - E64) <= 1e-5 * E64
@@ -167,20 +227,21 @@ def test_energy_grad_margin_radius(P):
 def test_energy_grad_deterministic(P):
     inst = synth.C4(8)
     d, xy = to_dev(P, inst)
-    row, col = P.build_neighbors(d, xy, 2.3, 0.0, True)
-    E1, g1 = P.energy_grad(d, xy, row, col)
-    E2, g2 = P.energy_grad(d, xy, row, col)
-    assert torch.equal(E1, E2) and torch.equal(g1, g2)
+    for form in (P.LIST_HALF, P.LIST_LOCAL16):
+        row, col = P.build_neighbors(d, xy, 2.3, 0.0, form)
+        E1, g1 = P.energy_grad(d, xy, row, col, form=form)
+        E2, g2 = P.energy_grad(d, xy, row, col, form=form)
+        assert torch.equal(E1, E2) and torch.equal(g1, g2)
 
 
 def test_energy_grad_bad_rows_give_nan(P):
     inst = synth.C1()
     d, xy = to_dev(P, inst)
     row, col = P.build_neighbors(d, xy, 2.3, 0.0, True)
-    E, _ = P.energy_grad(d, xy, row, col[:1].clone() if col.numel() > 1 else col)
+    E, _ = P.energy_grad(d, xy, row, col[:1].clone() if col.numel() > 1 else col, form=P.LIST_FULL)
     # a col_len shorter than the list makes the instance's range invalid
     E2 = torch.empty(1, dtype=torch.float32, device="cuda")
-    P.pecc_energy_grad(d, xy, row, col, max(0, col.numel() - 1), 1.0, E2, None)
+    P.pecc_energy_grad(d, xy, row, col, max(0, col.numel() - 1), P.LIST_FULL, 1.0, E2, None)
     if col.numel() > 0:
         assert torch.isnan(E2).all()
 
@@ -244,29 +305,83 @@ def c3_subset():
 BATCHES["C3sub"] = c3_subset
 
 
-@pytest.mark.parametrize("name", ["C1", "C2", "mixed", "crowded", "C3sub"])
-@pytest.mark.parametrize("iters", [1, 2, 3, 6])
-def test_descent_first_iterations_follow_oracle(P, name, iters):
-    inst = BATCHES[name]()
-    xg, res = run_gpu(P, inst, gpu_params(P, max_iter=iters, tau64=0.0))
+def follow_oracle(P, inst, iters, m=10, tau64=0.0, tol_per_iter=2e-5, name=""):
+    """The first iterations of the GPU descent against the FP64 oracle's:
+    the same number of accepted iterations, positions within tol_per_iter x
+    iters (relative to the layout's extent), the same energy to 1e-4."""
+    xg, res = run_gpu(P, inst, gpu_params(P, max_iter=iters, tau64=tau64, m=m))
+    worst = 0.0
     for b in range(inst.B):
         o0, o1 = inst.offset[b], inst.offset[b + 1]
         n = o1 - o0
         x64, r64, tr = oracle.descend(inst.instance(b).astype(np.float64), inst.R[b],
-                                      oracle.DescentParams(max_iter=iters, g_tol=0.0), trace=True)
+                                      oracle.DescentParams(max_iter=iters, g_tol=0.0, m=m), trace=True)
         if n == 0:
             continue
         if r64["E"] < 1e-10:
             # the overlap vanished: FP32 reaches E = 0 in its own number of
             # steps; both sides must end (numerically) overlap-free
-            o0, o1 = inst.offset[b], inst.offset[b + 1]
             assert oracle.energy(xg[o0:o1].astype(np.float64), inst.R[b]) < 1e-10
             continue
-        assert res["iters"][b] == r64["iters"], (b, res[b], r64)
+        assert res["iters"][b] == r64["iters"], (name, b, res[b], r64)
         scale = max(1.0, float(np.abs(x64).max()))
         err = np.abs(xg[o0:o1] - x64).max() / scale
-        assert err < 2e-5 * max(1, iters), (name, b, err)
+        worst = max(worst, err)
+        assert err < tol_per_iter * max(1, iters), (name, b, err)
         assert res["E32"][b] == pytest.approx(r64["E"], rel=1e-4, abs=1e-6)
+    return worst
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "mixed", "crowded", "C3sub"])
+@pytest.mark.parametrize("iters", [1, 2, 3, 6])
+def test_descent_first_iterations_follow_oracle(P, name, iters):
+    follow_oracle(P, BATCHES[name](), iters, name=name)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "C3sub"])
+@pytest.mark.parametrize("m,iters", [(2, 4), (2, 8), (3, 6), (3, 8), (1, 5)])
+def test_descent_history_eviction_follows_oracle(P, name, m, iters):
+    """Memory m below the iteration count: the history keeps the newest m
+    pairs (Eq. 10-11 over the last m), so the oldest pair leaves the
+    two-loop several times within the run."""
+    follow_oracle(P, BATCHES[name](), iters, m=m, name=name)
+
+
+@pytest.mark.parametrize("name", ["C2", "C3sub"])
+@pytest.mark.parametrize("iters", [12, 16])
+def test_descent_full_history_follows_oracle(P, name, iters):
+    """Past m = 10 iterations: every iteration after the tenth evicts the
+    oldest pair of a full history."""
+    follow_oracle(P, BATCHES[name](), iters, name=name)
+
+
+def near_feasible_batch():
+    # seven circles a little off the hexagonal optimum of n = 7 (R = 3)
+    # in a container 1e-3 wider, and the C3 restarts' first two instances
+    # after a short FP64 descent (small overlaps, E far below 1)
+    rng = synth.rng_for(21)
+    hexa = np.array([[0.0, 0.0]] + [[2 * np.cos(k * np.pi / 3), 2 * np.sin(k * np.pi / 3)]
+                                    for k in range(6)])
+    hexa = hexa * (1.0 - 2e-4) + rng.uniform(-1e-4, 1e-4, hexa.shape)
+    xs, Rs = [hexa], [3.0 + 1e-3]
+    rs = synth.C3_restarts()
+    for b in (0, 1):
+        x, _, _ = oracle.descend(rs.instance(b).astype(np.float64), rs.R[b],
+                                 oracle.DescentParams(max_iter=200))
+        xs.append(x)
+        Rs.append(float(rs.R[b]))
+    return synth.pack(xs, Rs)
+
+
+@pytest.mark.parametrize("iters", [1, 3, 6])
+def test_descent_fp64_regime_follows_oracle(P, iters):
+    """With tau64 above every start energy the GPU tests sufficient decrease
+    on FP64 energies from the first iteration (its FP32 directions, the
+    oracle's FP64 decisions): the trajectories agree like the FP32 ones."""
+    inst = near_feasible_batch()
+    E0 = [oracle.energy(inst.instance(b).astype(np.float64), inst.R[b]) for b in range(inst.B)]
+    assert max(E0) < 1.0 and min(E0) > 1e-12, E0
+    follow_oracle(P, inst, iters, tau64=10.0, name="near-feasible")
 
 
 def test_descent_batch_equals_single(P):
@@ -388,3 +503,21 @@ def test_c3_restart_batch_descends(P):
         o0, o1 = inst.offset[b], inst.offset[b + 1]
         assert oracle.verify(xg[o0:o1], inst.R[b])["feasible"]
     assert (f == (res["status"] == 1)).all()
+
+
+def test_descent_stalls_when_no_step_passes(P):
+    """c1 = 0.999 asks the first trial to realise almost all of the linear
+    decrease, which a curved energy never does at a full step; with no
+    halving allowed the line search fails at once: STALLED after 0
+    iterations, positions unchanged -- on the GPU as in the oracle."""
+    inst = mixed_batch(3, sizes=(20, 333, 1000))
+    prm = gpu_params(P, max_iter=50, c1=0.999, max_halvings=0)
+    xg, res = run_gpu(P, inst, prm)
+    for b in range(inst.B):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                     oracle.DescentParams(max_iter=50, g_tol=0.0, c1=0.999,
+                                                          max_halvings=0))
+        assert r64["status"] == "STALLED" and r64["iters"] == 0, r64
+        assert P.STATUS[res["status"][b]] == "STALLED" and res["iters"][b] == 0, res[b]
+        assert np.array_equal(xg[o0:o1], inst.instance(b))

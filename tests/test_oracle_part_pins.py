@@ -125,7 +125,7 @@ def test_colour_major_visits_equal_grid_descent(which):
     b, k = grid_relabelled(x, R, 4)
     P = oracle.DescentParams(g_tol=0.0)
     xa, ra, ta = oracle.gbo_seq_descend(x, R, b, k, P, max_outer=4, trace=True)
-    xb, rb, tb = oracle.gbo_descend(x, R, P, blocks=4, max_outer=4, jacobi=False, skin_half=0.0,
+    xb, rb, tb = oracle.gbo_descend(x, R, P, blocks=4, max_outer=4, jacobi=False,
                                     trace=True)
     assert np.array_equal(xa, xb) and np.array_equal(ta, tb)
     assert (ra["visits"], ra["evals"], ra["gsum"]) == (rb["visits"], rb["evals"], rb["gsum"])
