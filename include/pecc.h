@@ -199,6 +199,25 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy,
                        void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * pecc_lbfgs_descend without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The descent's scratch memory (its work queue,
+ * num_instances + 1 int32) is a fixed array inside the library, one per
+ * device, held until the process ends: PECC_NOALLOC_MAX_INSTANCES + 1 words
+ * (256 KiB).  The call allocates nothing; the caller still owns xy and out.
+ * Same arguments, results and errors as pecc_lbfgs_descend, bit for bit,
+ * plus PECC_ERR_INVALID when num_instances exceeds
+ * PECC_NOALLOC_MAX_INSTANCES.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, other host
+ * threads) race and must be serialised by the caller; consecutive calls on
+ * one stream are fine (the queue is re-initialised by a kernel each call).
+ * ------------------------------------------------------------------------ */
+#define PECC_NOALLOC_MAX_INSTANCES 65536
+int pecc_lbfgs_descend_noalloc(const pecc_instances *inst, float *xy,
+                               const pecc_descent_params *params /*host*/,
+                               pecc_descent_result *out /*device [B]*/, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Geometric batch descent (Alg. 1 with the batch energy of Eq. 7 and the
  * limited-memory reading of Eq. 8-11) for every instance of the batch, one
  * persistent launch.  The circles are partitioned once, from the input

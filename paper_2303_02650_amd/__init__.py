@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpecc.so")
 
 PECC_MAX_N = 1024
 PECC_MAX_M = 10
+PECC_NOALLOC_MAX_INSTANCES = 65536
 # neighbor-list forms (PECC_LIST_*)
 LIST_HALF, LIST_FULL, LIST_LOCAL16 = 0, 1, 2
 STATUS = {0: "RUNNING", 1: "FEASIBLE", 2: "STATIONARY", 3: "CONVERGED", 4: "STALLED",
@@ -78,6 +79,8 @@ _sig = {
     "pecc_lbfgs_descend_workspace_size": (C.c_int, [_P(pecc_instances), _P(C.c_size_t)]),
     "pecc_lbfgs_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pecc_lbfgs_descend_noalloc": (C.c_int, [_P(pecc_instances), C.c_void_p,
+                                             _P(pecc_descent_params), C.c_void_p, C.c_void_p]),
     "pecc_verify": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pecc_gbo_descend_workspace_size": (C.c_int, [_P(pecc_instances), C.c_int32, _P(C.c_size_t)]),
@@ -207,6 +210,11 @@ def pecc_lbfgs_descend(inst, xy, params: pecc_descent_params, out, workspace, st
     _check(_lib.pecc_lbfgs_descend(C.byref(inst.c()), _ptr(xy), C.byref(params), _ptr(out),
                                    _ptr(workspace), workspace.numel() * workspace.element_size(),
                                    _stream(stream)))
+
+
+def pecc_lbfgs_descend_noalloc(inst, xy, params: pecc_descent_params, out, stream=None):
+    _check(_lib.pecc_lbfgs_descend_noalloc(C.byref(inst.c()), _ptr(xy), C.byref(params), _ptr(out),
+                                           _stream(stream)))
 
 
 def pecc_gbo_descend_workspace_size(inst: DeviceInstances, blocks: int) -> int:

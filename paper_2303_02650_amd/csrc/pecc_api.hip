@@ -213,6 +213,28 @@ int pecc_lbfgs_descend(const pecc_instances *inst, float *xy, const pecc_descent
                      fn);
 }
 
+int pecc_lbfgs_descend_noalloc(const pecc_instances *inst, float *xy,
+                               const pecc_descent_params *p, pecc_descent_result *out,
+                               hipStream_t stream)
+{
+    const char *fn = "pecc_lbfgs_descend_noalloc";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (inst->num_instances > PECC_NOALLOC_MAX_INSTANCES)
+        return fail(PECC_ERR_INVALID, "%s: %d instances exceed the limit of %d", fn,
+                    inst->num_instances, PECC_NOALLOC_MAX_INSTANCES);
+    if (!p || !out) return fail(PECC_ERR_INVALID, "%s: params and out must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    pecc::DescentArgs a;
+    rc = descent_args(p, fn, &a);
+    if (rc) return rc;
+    const int grid = pecc::descend_grid(inst->num_instances);
+    return check_hip(pecc::launch_descend_noalloc(inst->offset, inst->R, inst->R64, xy,
+                                                  inst->num_instances, inst->total_n, a, out,
+                                                  grid, stream),
+                     fn);
+}
+
 int pecc_adjust_container_workspace_size(const pecc_instances *inst, size_t *bytes)
 {
     return pecc_lbfgs_descend_workspace_size(inst, bytes);
@@ -621,6 +643,7 @@ int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
 static_assert(sizeof(pecc_descent_result) == 48, "result layout");
 static_assert(sizeof(pecc_descent_params) == 64, "params layout");
 static_assert(PECC_MAX_BATCHES == pecc::kMaxSeqBatches, "batch limit");
+static_assert(PECC_NOALLOC_MAX_INSTANCES == pecc::kNoAllocMaxInstances, "no-alloc limit");
 static_assert(PECC_LIST_HALF == pecc::kListHalf && PECC_LIST_FULL == pecc::kListFull &&
               PECC_LIST_LOCAL16 == pecc::kListLocal16, "list forms");
 static_assert(sizeof(pecc_adam_params) == 16, "adam params layout");

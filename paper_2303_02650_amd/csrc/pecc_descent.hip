@@ -1362,6 +1362,51 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
     return hipGetLastError();
 }
 
+// The descent's only scratch memory is its work queue (a counter and the
+// instance order, B + 1 int32).  For callers that cannot allocate, the
+// library keeps one queue per device in a fixed array: kNoAllocMaxInstances
+// + 1 words (256 KiB), held by every device the library runs on until the
+// process ends.  Host code never passes the array's name to a kernel (in host
+// code it is a stand-in, not a device address): the device address comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+// The queue is set by a kernel at every call (queue_init_kernel), so nothing
+// carries over from the previous call; calls that overlap on one device
+// share the array and race.
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxInstances + 1];
+
+namespace {
+std::atomic<int32_t *> g_scratch_ptr[kMaxDevices];
+
+// The array's device address on the current device (looked up once per device).
+hipError_t noalloc_queue(int32_t **queue)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    int32_t *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        e = hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev].store(p, std::memory_order_release);   // the same value from any thread
+    }
+    *queue = p;
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_descend_noalloc(const int32_t *offset, const float *R, const double *R64,
+                                  float *xy, int B, int64_t total_n, const DescentArgs &a,
+                                  void *out, int grid, hipStream_t s)
+{
+    if (B > kNoAllocMaxInstances) return hipErrorInvalidValue;
+    int32_t *queue = nullptr;
+    const hipError_t e = noalloc_queue(&queue);
+    if (e != hipSuccess) return e;
+    return launch_descend(offset, R, R64, xy, B, total_n, a, out, queue, grid, s);
+}
+
 hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B,
                          int64_t total_n, const DescentArgs &a, float *Rout, void *out,
                          int32_t *queue, int grid, hipStream_t s)

@@ -46,6 +46,13 @@ hipError_t launch_descend(const int32_t *offset, const float *R, const double *R
 
 int descend_grid(int B);   // persistent workgroups to launch for B instances
 
+// The same descent with its work queue in a library-held array (no
+// allocation anywhere): at most kNoAllocMaxInstances instances.
+constexpr int kNoAllocMaxInstances = 65536;
+hipError_t launch_descend_noalloc(const int32_t *offset, const float *R, const double *R64,
+                                  float *xy, int B, int64_t total_n, const DescentArgs &a,
+                                  void *out, int grid, hipStream_t s);
+
 // Container adjustment: the descent with the radius as a variable (Rout[B]
 // receives the final radii; the initial ones come from R).
 hipError_t launch_adjust(const int32_t *offset, const float *R, float *xy, int B,
