@@ -760,6 +760,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // circle and always takes the FP64 energies
             const bool masked = SEQ && visits && req != kReqTotal;
             const bool want64 = fp64 || (SEQ && req == kReqTotal);
+            // the FP32 energy of unit circles decides the switch into the
+            // FP64 regime and nothing else
+            const bool want_e1 = !ADJ && !fp64;
             bool inb[kCPT];
 #pragma unroll
             for (int c = 0; c < kCPT; ++c) inb[c] = !masked || batc_of(c) == cb;
@@ -881,7 +884,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             if constexpr (SEQ) if (masked) hf = hf || sq.bat[j] != cb;
                             float l2;
                             const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
-                                                          ecA[c], e1cA[c], gxA[c], gyA[c], l2);
+                                                          ecA[c], e1cA[c], gxA[c], gyA[c], l2,
+                                                          want_e1);
                             // FP64 energies only where FP32 sees (nearly) an overlap:
                             // outside a 1e-5 band the FP64 terms are zero
                             if (want64 && hf && l2 < four_r2_band)
@@ -894,7 +898,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             for (int c = 0; c < kCPT; ++c) {
                 const int i = tid + c * kDB;
                 const float2 q = xt[c];
-                float gx = gxA[c], gy = gyA[c];
+                // the list sweep's sums carry the pair terms divided by -2
+                float gx = -2.f * gxA[c], gy = -2.f * gyA[c];
                 if (act[c] && inb[c]) {
                     float ec = ecA[c], e1c = e1cA[c];
                     double eoc = eocA[c], etc = etcA[c];
@@ -1067,13 +1072,22 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // all reads before the writes, so that the LDS round trips of
+                // the seven entries overlap (read-write pairs would serialise:
+                // the two buffers of Bm are one array to the compiler)
+                constexpr int kGR = (kNB * kNB + kWave - 1) / kWave;
+                float gv[kGR];
 #pragma unroll
-                for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
+                for (int r = 0; r < kGR; ++r) {
                     const int ent = lane + kWave * r;
-                    if (ent < kNB * kNB) {
-                        const int src = sh.bsrc[push ? 1 : 0][ent];
-                        sh.Bm[nxt][ent] = (src & 0x8000) ? sh.tot_s[par][src & 0x7fff] : sh.Bm[cur][src];
-                    }
+                    const int src = sh.bsrc[push ? 1 : 0][ent < kNB * kNB ? ent : 0];
+                    const float *from = (src & 0x8000) ? &sh.tot_s[par][src & 0x7fff] : &sh.Bm[cur][src];
+                    gv[r] = *from;
+                }
+#pragma unroll
+                for (int r = 0; r < kGR; ++r) {
+                    const int ent = lane + kWave * r;
+                    if (ent < kNB * kNB) sh.Bm[nxt][ent] = gv[r];
                 }
                 cur = nxt;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

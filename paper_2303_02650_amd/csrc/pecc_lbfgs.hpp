@@ -67,7 +67,9 @@ __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], cons
 {
     if (v == sE) return e;
     if (v == sE1) return e1;
-    float acc = 0.0f;
+    // the first circle's product starts the sum (adding it to 0 would cost
+    // an instruction per slot and round nothing)
+    float acc;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         float t;
@@ -83,7 +85,7 @@ __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], cons
         else if (v == sYcYc) t = dot2(yc[c], yc[c]);
         else if (v == sScG) t = dot2(sc[c], gt[c]);
         else t = dot2(yc[c], gt[c]);   // sYcG
-        acc += t;
+        acc = c == 0 ? t : acc + t;
     }
     return acc;
 }
@@ -328,22 +330,32 @@ __device__ __forceinline__ double sqrt64_from32(double m2, float l32, float il)
     return l;
 }
 
-// pair_term32 that also returns the FP32 1/l of pairs inside the FP64 band
-// (l2 < four_r2_band, 0 elsewhere and at l2 = 0) and l2, the seeds of
-// pair_term64s.  The FP32 terms are those of pair_term32, bit for bit.
+// The list sweep's FP32 pair term of circle i (at q) with circle j (at pj),
+// as pair_term32 but with the gradient term divided by -2: gx, gy receive
+// (d / l) (c_i - c_j), and the caller multiplies the sum by -2 -- a scaling
+// by a power of two, exact, so the result has pair_term32's bits.  Returns
+// the FP32 1/l (from max(l^2, FLT_MIN): coincident centres give d = 2 rad
+// and a zero term without a test of their own) and l2, the seeds of
+// pair_term64s.
 __device__ __forceinline__ float pair_term32s(float2 q, float2 pj, bool count_e, float two_r,
                                               float four_r2, float four_r2_band, float &e,
-                                              float &e1, float &gx, float &gy, float &l2o)
+                                              float &e1, float &gx, float &gy, float &l2o,
+                                              bool want_e1 = true)
 {
+    (void)four_r2_band;
     const float dx = q.x - pj.x, dy = q.y - pj.y;
     const float l2 = dx * dx + dy * dy;
     const bool ov = l2 < four_r2;
-    const float il = (l2 < four_r2_band && l2 > 0.f) ? __builtin_amdgcn_rsqf(l2) : 0.f;
+    const float il = __builtin_amdgcn_rsqf(fmaxf(l2, 1.17549435e-38f));
     const float d = ov ? two_r - l2 * il : 0.f;
-    const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
     e += count_e ? d * d : 0.f;
-    e1 += count_e ? d1 * d1 : 0.f;
-    const float kf = -2.f * d * il;
+    // the unit-circle energy (wave-uniform want_e1: only its caller's switch
+    // into the FP64 regime reads it)
+    if (want_e1) {
+        const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
+        e1 += count_e ? d1 * d1 : 0.f;
+    }
+    const float kf = d * il;
     gx += kf * dx;
     gy += kf * dy;
     l2o = l2;
