@@ -51,6 +51,7 @@ struct DescentShared {
     double red64[2][kDW][2];
     float Bm[2][kNB * kNB];
     float tot_s[2][kWave];
+    float rho[2][kMM];             // 1 / s_j'y_j of the Gram buffer of the same index
     uint16_t bsrc[2][kNB * kNB];   // Gram update sources, see gram_source
     int scan_tmp[kDW + 1];
     int flag[2];
@@ -725,6 +726,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         };
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
+        for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
         if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0; }
 
         // container adjustment state (uniform): radius, its gradient and
@@ -740,6 +742,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // the previous round's reads of B before it is cleared
             __syncthreads();
             for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
+            for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
             k = 0; cur = 0; it = 0; h = 0; status = 0;
             req = kReqInit;
             hR_v = 0.f;
@@ -1089,6 +1092,17 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     const int ent = lane + kWave * r;
                     if (ent < kNB * kNB) sh.Bm[nxt][ent] = gv[r];
                 }
+                if constexpr (!SEQ) {
+                    // 1 / s_j'y_j follows the Gram entries (shifted on a push,
+                    // the newest from the new entry): the two-loop reads them
+                    // instead of dividing every iteration
+                    if (lane < kMM) {
+                        const float keep = sh.rho[cur][lane < kMM - 1 ? lane + 1 : lane];
+                        const float sy = lane_value(tot, sScYc);
+                        sh.rho[nxt][lane] = !push ? sh.rho[cur][lane]
+                                                  : lane < kMM - 1 ? keep : 1.f / sy;
+                    }
+                }
                 cur = nxt;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -1207,7 +1221,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
                 const bool live = lane < 2 * kMM && jp >= kMM - k;
                 const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
-                const float rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
+                float rho_v;
+                if constexpr (SEQ) {
+                    rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
+                } else {
+                    rho_v = sh.rho[cur][jq];
+                    rho_v = live ? rho_v : 0.f;
+                }
                 float acc = Bc[kG];                                   // (B q)_l with q = g
                 float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
     #pragma unroll
@@ -1269,7 +1289,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if constexpr (ADJ) pR = -gR;
                 gp = -gg;
             }
-            alpha = k > 0 ? 1.f : 1.f / fmaxf(1.f, gn);
+            if (k > 0) alpha = 1.f;
+            else alpha = 1.f / fmaxf(1.f, gn);
             h = 0;
             req = kReqTrial;
         }
