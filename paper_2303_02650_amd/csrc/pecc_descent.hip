@@ -58,6 +58,13 @@ struct DescentShared {
     int over;                      // a circle had more than ELL neighbors
     int work;
     int cell_evals;                // evaluations over the cell grid (instance)
+    // whole-instance descent: what the deciding wave leaves for the others
+    int dec_flags;                 // kDec* bits
+    int dec_req;                   // what the next evaluation is for
+    int dec_fp64;                  // FP64 regime from the next evaluation on
+    float dec_alpha;               // step length of the next trial
+    float dec_gam;                 // gamma of the direction
+    float coef[2][kMM];            // coefficients of s_j and y_j in the direction
 };
 
 // Batch descent only: the saved Gram matrix of every batch, batch ids and
@@ -241,6 +248,8 @@ struct NoShared {
 
 // Evaluation requests of the descent's state machine.
 enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2, kReqTotal = 3 };
+// outcome of an evaluation in the whole-instance descent
+enum : int { kDecAccept = 1, kDecPush = 2, kDecStop = 4, kDecNext = 8, kDecSteepest = 16 };
 
 // ADJ: container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins
 // the variables, the objective is U = E + lambda R^2 and A.rounds
@@ -282,6 +291,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     constexpr bool ADJ = MODE == kModeAdj;
     constexpr bool DENSE = MODE == kModeDense;
     constexpr bool SEQ = MODE == kModeSeq || DENSE;
+    // whole instance: one wave takes the uniform decisions of an evaluation
+    constexpr bool SOLO = MODE == kModeWhole;
     constexpr int ELL = SEQ ? kEllSeq : kEll;
     __shared__ DescentShared<ELL> sh;
     __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
@@ -725,6 +736,103 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
         };
 
+        // Gram matrix of the updated basis: slot totals to LDS (every wave
+        // that calls it writes the same bits), then each lane fills 7 of the
+        // 21 x 21 entries of the other buffer, which becomes current
+        auto gram_update = [&](float tot, int par, bool push, int lane) {
+            const int nxt = cur ^ 1;
+            sh.tot_s[par][lane] = tot;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // all reads before the writes, so that the LDS round trips of
+            // the seven entries overlap (read-write pairs would serialise:
+            // the two buffers of Bm are one array to the compiler)
+            constexpr int kGR = (kNB * kNB + kWave - 1) / kWave;
+            float gv[kGR];
+#pragma unroll
+            for (int r = 0; r < kGR; ++r) {
+                const int ent = lane + kWave * r;
+                const int src = sh.bsrc[push ? 1 : 0][ent < kNB * kNB ? ent : 0];
+                const float *from = (src & 0x8000) ? &sh.tot_s[par][src & 0x7fff] : &sh.Bm[cur][src];
+                gv[r] = *from;
+            }
+#pragma unroll
+            for (int r = 0; r < kGR; ++r) {
+                const int ent = lane + kWave * r;
+                if (ent < kNB * kNB) sh.Bm[nxt][ent] = gv[r];
+            }
+            if constexpr (!SEQ) {
+                // 1 / s_j'y_j follows the Gram entries (shifted on a push,
+                // the newest from the new entry): the two-loop reads them
+                // instead of dividing every iteration
+                if (lane < kMM) {
+                    const float keep = sh.rho[cur][lane < kMM - 1 ? lane + 1 : lane];
+                    const float sy = lane_value(tot, sScYc);
+                    sh.rho[nxt][lane] = !push ? sh.rho[cur][lane]
+                                              : lane < kMM - 1 ? keep : 1.f / sy;
+                }
+            }
+            cur = nxt;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        // Two-loop recursion on B. Lane l holds row l of B (the basis
+        // s_0..s_9, y_0..y_9, g), so acc = (B c) for the current coefficient
+        // vector c is one FMA per lane per step: q = g - sum_i a_i y_i gives
+        // acc -= a_j B[l][y_j], r = gamma q + sum_j (a_j - b_j) s_j gives
+        // acc += (a_j - b_j) B[l][s_j].  s_j'q and y_j'r are then single lanes
+        // of acc (one readlane per step).  The per-pair scalars stay
+        // lane-indexed in VGPRs (lane j: rho_j, a_j, the s_j coefficient; lane
+        // 10 + j: rho_j and a_j again).  Returns g'p with p = -r; cs_v: the
+        // coefficient of s_j at lane j; alph_v: a_j at lane j.
+        auto two_loop = [&](int lane, float &cs_out, float &alph_out, float &gam_out) -> float {
+            float Bc[kNB];
+#pragma unroll
+            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
+            const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
+            const bool live = lane < 2 * kMM && jp >= kMM - k;
+            const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
+            float rho_v;
+            if constexpr (SEQ) {
+                rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
+            } else {
+                rho_v = sh.rho[cur][jq];
+                rho_v = live ? rho_v : 0.f;
+            }
+            float acc = Bc[kG];                                   // (B q)_l with q = g
+            float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
+#pragma unroll
+            for (int j = kMM - 1; j >= 0; --j) {
+                if (j >= kMM - k) {
+                    const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
+                    if (jp == j) alph_v = a;
+                    acc -= a * Bc[kMM + j];
+                }
+            }
+            float gam = 1.f;
+            if (k > 0) {
+                const float sy = lane_value(Bc[kMM - 1], 2 * kMM - 1);
+                const float yy = lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
+                gam = sy / yy;
+            }
+            acc *= gam;                                           // (B r)_l with r = gamma q
+            float cs_v = 0.f;                                     // coefficient of s_j at lane j
+#pragma unroll
+            for (int j = 0; j < kMM; ++j) {
+                if (j >= kMM - k) {
+                    const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
+                    if (lane == j) cs_v = c;
+                    acc += c * Bc[j];
+                }
+            }
+            cs_out = cs_v;
+            alph_out = alph_v;
+            gam_out = gam;
+            return -lane_value(acc, kG);                          // g'p = -g'r
+        };
+
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
         for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
         if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0; }
@@ -972,6 +1080,146 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (lane == 0) { sh.red64[par][wv][0] = wo; sh.red64[par][wv][1] = wt; }
             }
             __syncthreads();                                            // B2
+            if constexpr (SOLO) {
+                // ---- one wave decides ----------------------------------------
+                // The uniform chain (slot totals, line search, Gram matrix,
+                // stop tests, two-loop) runs on wave 0 alone: on every wave it
+                // would share each SIMD with a copy of itself.  The outcome
+                // reaches the other waves through LDS behind one barrier.
+                if (wv == 0) {
+                    float tot = 0.f;
+#pragma unroll
+                    for (int w = 0; w < kDW; ++w) tot += sh.red[par][w][lane];
+                    double so = 0.0, st = 0.0;
+                    if (want64) {
+                        // lane w holds wave w's FP64 sums; added in wave order
+                        const int wl = lane < kDW ? lane : 0;
+                        const double vo = sh.red64[par][wl][0], vt = sh.red64[par][wl][1];
+#pragma unroll
+                        for (int w = 0; w < kDW; ++w) {
+                            so += lane_value64(vo, w);
+                            st += lane_value64(vt, w);
+                        }
+                    }
+                    const float Et = lane_value(tot, sE);
+                    const float E1t = lane_value(tot, sE1);
+                    int fl = 0;
+                    bool accept = false, push = false;
+                    if (req == kReqTrial) {
+                        const bool ok = fp64 ? so <= E64o + (double)A.c1 * (double)alpha * (double)gp
+                                             : Et <= E + A.c1 * alpha * gp;
+                        if (ok) {
+                            accept = true;
+                            const float sy = lane_value(tot, sScYc), yy = lane_value(tot, sYcYc);
+                            push = sy > A.eps_curv * yy;
+                        } else {
+                            alpha *= 0.5f;
+                            if (++h > A.max_halvings) { status = 4; fl = kDecStop; }   // STALLED
+                            else fl = kDecNext;
+                        }
+                    } else if (req == kReqInit) {
+                        accept = true;   // g and the g row of B from this evaluation
+                    } else {             // kReqFp64: FP64 energies of the current point
+                        E64o = so;
+                        E64t = st;
+                    }
+                    if (accept) {
+                        fl = kDecAccept | (push ? kDecPush : 0);
+                        gram_update(tot, par, push, lane);
+                        if (push) k = k + 1 > A.m ? A.m : k + 1;
+                        if (req == kReqTrial) ++it;
+                        E = Et;
+                        if (fp64) { E64o = so; E64t = st; }
+                        // FP64 regime once either FP32 energy is small
+                        if (!fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
+                            fp64 = true;
+                            req = kReqFp64;          // FP64 energies of x before going on
+                            fl |= kDecNext;
+                        }
+                    }
+                    if (!(fl & (kDecNext | kDecStop))) {
+                        // ---- top of an iteration: stop tests, direction
+                        const float gg = sh.Bm[cur][kG * kNB + kG];
+                        const float gn = sqrtf(fmaxf(gg, 0.f));
+                        const double Eacc = fp64 ? E64o : (double)E;
+                        if (!isfinite(E) || !isfinite(gn)) status = 6;
+                        else if (fp64 && E64t < A.e_feasible) status = 1;
+                        else if (gn <= A.g_tol) status = 2;
+                        else if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) status = 3;
+                        else {
+                            if (lane == it % (W + 1)) ehist = Eacc;
+                            if (it >= A.max_iter) status = 5;
+                        }
+                        if (status != 0) {
+                            fl |= kDecStop;
+                        } else {
+                            float cs_v, alph_v, gam;
+                            gp = two_loop(lane, cs_v, alph_v, gam);
+                            if (k > 0 && !(gp < 0.f)) {
+                                k = 0;
+                                gp = -gg;
+                                fl |= kDecSteepest;
+                            }
+                            if (k > 0) alpha = 1.f;
+                            else alpha = 1.f / fmaxf(1.f, gn);
+                            h = 0;
+                            req = kReqTrial;
+                            if (lane < kMM) {
+                                sh.coef[0][lane] = cs_v;
+                                sh.coef[1][lane] = -gam * alph_v;
+                            }
+                            if (lane == 0) sh.dec_gam = gam;
+                        }
+                    }
+                    if (lane == 0) {
+                        sh.dec_flags = fl;
+                        sh.dec_req = req;
+                        sh.dec_fp64 = fp64 ? 1 : 0;
+                        sh.dec_alpha = alpha;
+                    }
+                }
+                __syncthreads();                                        // B3
+                const int fl = __builtin_amdgcn_readfirstlane(sh.dec_flags);
+                req = __builtin_amdgcn_readfirstlane(sh.dec_req);
+                fp64 = __builtin_amdgcn_readfirstlane(sh.dec_fp64) != 0;
+                alpha = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                      __builtin_bit_cast(int, sh.dec_alpha)));
+                if (fl & kDecAccept) {
+                    const bool push = (fl & kDecPush) != 0;
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        if (push) {
+#pragma unroll
+                            for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
+                            S[kMM - 1][c] = sc[c];
+                            Y[kMM - 1][c] = yc[c];
+                        }
+                        x[c] = xt[c];
+                        g[c] = gt[c];
+                    }
+                }
+                if (fl & kDecStop) break;
+                if (fl & kDecNext) continue;
+                // ---- direction p = -(gamma g + sum_j cs_j s_j + cy_j y_j)
+                if (fl & kDecSteepest) {
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) p[c] = make_float2(-g[c].x, -g[c].y);
+                } else {
+                    const float gam = sh.dec_gam;
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        float px = -gam * g[c].x, py = -gam * g[c].y;
+#pragma unroll
+                        for (int j = 0; j < kMM; ++j) {
+                            const float csj = sh.coef[0][j], cyj = sh.coef[1][j];
+                            px -= csj * S[j][c].x + cyj * Y[j][c].x;
+                            py -= csj * S[j][c].y + cyj * Y[j][c].y;
+                        }
+                        p[c] = make_float2(px, py);
+                    }
+                }
+                continue;
+            }
             float tot = 0.f;
 #pragma unroll
             for (int w = 0; w < kDW; ++w) tot += sh.red[par][w][lane];
@@ -1067,46 +1315,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 E64t = st;
             }
             if (accept) {
-                // ---- Gram matrix of the updated basis (every wave) -----------
-                // slot totals to LDS (every wave writes the same bits), then
-                // each lane fills 7 of the 21 x 21 entries
-                const int nxt = cur ^ 1;
-                sh.tot_s[par][lane] = tot;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // all reads before the writes, so that the LDS round trips of
-                // the seven entries overlap (read-write pairs would serialise:
-                // the two buffers of Bm are one array to the compiler)
-                constexpr int kGR = (kNB * kNB + kWave - 1) / kWave;
-                float gv[kGR];
-#pragma unroll
-                for (int r = 0; r < kGR; ++r) {
-                    const int ent = lane + kWave * r;
-                    const int src = sh.bsrc[push ? 1 : 0][ent < kNB * kNB ? ent : 0];
-                    const float *from = (src & 0x8000) ? &sh.tot_s[par][src & 0x7fff] : &sh.Bm[cur][src];
-                    gv[r] = *from;
-                }
-#pragma unroll
-                for (int r = 0; r < kGR; ++r) {
-                    const int ent = lane + kWave * r;
-                    if (ent < kNB * kNB) sh.Bm[nxt][ent] = gv[r];
-                }
-                if constexpr (!SEQ) {
-                    // 1 / s_j'y_j follows the Gram entries (shifted on a push,
-                    // the newest from the new entry): the two-loop reads them
-                    // instead of dividing every iteration
-                    if (lane < kMM) {
-                        const float keep = sh.rho[cur][lane < kMM - 1 ? lane + 1 : lane];
-                        const float sy = lane_value(tot, sScYc);
-                        sh.rho[nxt][lane] = !push ? sh.rho[cur][lane]
-                                                  : lane < kMM - 1 ? keep : 1.f / sy;
-                    }
-                }
-                cur = nxt;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                gram_update(tot, par, push, lane);
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     if (!DENSE && push && inb[c]) {
@@ -1207,55 +1416,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 gp = dense_direction();
             } else {
                 // ================= direction: two-loop recursion on B ===============
-                // Lane l holds row l of B (the basis s_0..s_9, y_0..y_9, g), so
-                // acc = (B c) for the current coefficient vector c is one FMA per
-                // lane per step: q = g - sum_i a_i y_i gives acc -= a_j B[l][y_j],
-                // r = gamma q + sum_j (a_j - b_j) s_j gives acc += (a_j - b_j) B[l][s_j].
-                // s_j'q and y_j'r are then single lanes of acc (one readlane per
-                // step).  The per-pair scalars stay lane-indexed in VGPRs (lane j:
-                // rho_j, a_j, the s_j coefficient; lane 10 + j: rho_j and a_j again)
-                // and are read out only where the direction is formed.
-                float Bc[kNB];
-    #pragma unroll
-                for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
-                const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
-                const bool live = lane < 2 * kMM && jp >= kMM - k;
-                const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
-                float rho_v;
-                if constexpr (SEQ) {
-                    rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
-                } else {
-                    rho_v = sh.rho[cur][jq];
-                    rho_v = live ? rho_v : 0.f;
-                }
-                float acc = Bc[kG];                                   // (B q)_l with q = g
-                float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
-    #pragma unroll
-                for (int j = kMM - 1; j >= 0; --j) {
-                    if (j >= kMM - k) {
-                        const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
-                        if (jp == j) alph_v = a;
-                        acc -= a * Bc[kMM + j];
-                    }
-                }
-                float gam = 1.f;
-                if (k > 0) {
-                    const float sy = lane_value(Bc[kMM - 1], 2 * kMM - 1);
-                    const float yy = lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
-                    gam = sy / yy;
-                }
-                acc *= gam;                                           // (B r)_l with r = gamma q
-                float cs_v = 0.f;                                     // coefficient of s_j at lane j
-    #pragma unroll
-                for (int j = 0; j < kMM; ++j) {
-                    if (j >= kMM - k) {
-                        const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
-                        if (lane == j) cs_v = c;
-                        acc += c * Bc[j];
-                    }
-                }
+                float cs_v, alph_v, gam;
+                gp = two_loop(lane, cs_v, alph_v, gam);
                 {
-                    gp = -lane_value(acc, kG);                        // g'p = -g'r
                     const float cy_v = -gam * alph_v;                 // coefficient of y_j at lane j
     #pragma unroll
                     for (int c = 0; c < kCPT; ++c) {

@@ -119,6 +119,14 @@ __device__ __forceinline__ float lane_value(float v, int l)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
+__device__ __forceinline__ double lane_value64(double v, int l)
+{
+    const long long bits = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 // Sum over the 64 lanes, returned wave-uniform.  Every wave adds in the same
 // order, so every wave gets the same bits.
 __device__ __forceinline__ float wave_sum_dpp(float v)
