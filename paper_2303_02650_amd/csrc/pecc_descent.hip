@@ -298,7 +298,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int wv = tid / kWave;
+    // wave index, wave-uniform to the compiler (branches on it stay scalar)
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int q = tid; q < 2 * kNB * kNB; q += kDB)
         sh.bsrc[q / (kNB * kNB)][q % (kNB * kNB)] = gram_source(q % (kNB * kNB), q >= kNB * kNB);
     const float c2lo = (float)(A.c2 * (1.0 - 1e-5)), c2hi = (float)(A.c2 * (1.0 + 1e-5));
@@ -788,9 +789,11 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // 10 + j: rho_j and a_j again).  Returns g'p with p = -r; cs_v: the
         // coefficient of s_j at lane j; alph_v: a_j at lane j.
         auto two_loop = [&](int lane, float &cs_out, float &alph_out, float &gam_out) -> float {
+            // lanes past row 20 read row 20 again: their values are never read
             float Bc[kNB];
+            const int lr = lane < kNB ? lane : kNB - 1;
 #pragma unroll
-            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? sh.Bm[cur][a2 * kNB + lane] : 0.f;
+            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = sh.Bm[cur][a2 * kNB + lr];
             const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
             const bool live = lane < 2 * kMM && jp >= kMM - k;
             const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
@@ -803,13 +806,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             float acc = Bc[kG];                                   // (B q)_l with q = g
             float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
+            // every pair slot in straight-line code: a slot without a pair
+            // has rho = 0, so its a_j and coefficient are 0 and acc keeps its
+            // bits (acc - 0 * B = acc for finite B)
 #pragma unroll
             for (int j = kMM - 1; j >= 0; --j) {
-                if (j >= kMM - k) {
-                    const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
-                    if (jp == j) alph_v = a;
-                    acc -= a * Bc[kMM + j];
-                }
+                const float a = lane_value(rho_v * acc, j);         // rho_j s_j'q
+                if (jp == j) alph_v = a;
+                acc -= a * Bc[kMM + j];
             }
             float gam = 1.f;
             if (k > 0) {
@@ -821,11 +825,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             float cs_v = 0.f;                                     // coefficient of s_j at lane j
 #pragma unroll
             for (int j = 0; j < kMM; ++j) {
-                if (j >= kMM - k) {
-                    const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
-                    if (lane == j) cs_v = c;
-                    acc += c * Bc[j];
-                }
+                const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
+                if (lane == j) cs_v = c;
+                acc += c * Bc[j];
             }
             cs_out = cs_v;
             alph_out = alph_v;
