@@ -145,6 +145,24 @@ int pecc_lbfgs_descend_workspace_size(const pecc_instances *inst, size_t *bytes)
 
 namespace {
 
+// Largest float x >= 0 with sqrtf(x) <= t.  Both host and device square
+// roots are correctly rounded, hence monotonic, so sqrtf(x) <= t exactly
+// when x <= sqrt_threshold(t).
+float sqrt_threshold(float t)
+{
+    if (!(t >= 0.f)) return -1.f;
+    if (isinf(t)) return INFINITY;
+    float x = t * t;
+    if (isinf(x)) x = 3.40282347e38f;
+    while (x > 0.f && sqrtf(x) > t) x = nextafterf(x, 0.f);
+    for (;;) {
+        const float up = nextafterf(x, INFINITY);
+        if (isinf(up) || sqrtf(up) > t) break;
+        x = up;
+    }
+    return x;
+}
+
 // Validates the descent constants and derives the kernels' form of them.
 int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs *a)
 {
@@ -173,6 +191,7 @@ int descent_args(const pecc_descent_params *p, const char *fn, pecc::DescentArgs
     a->eps_curv = p->eps_curv;
     a->h_req = (float)((p->cell_size > 0.f ? p->cell_size : p->cutoff) * (1.0 + 1e-4));
     a->g_tol = p->g_tol;
+    a->g_tol_sq = sqrt_threshold(p->g_tol);
     a->ftol = p->ftol;
     a->rad = (float)rad;
     a->c2 = (double)p->cutoff * (double)p->cutoff;

@@ -455,6 +455,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         float E = 0.0f, gp = 0.f, alpha = 0.f;
         double ehist = 0.0;               // lane w: energy of iteration w mod (W+1)
         int status = 0, it = 0, h = 0;
+        int itw = 0;                      // it mod (W + 1), kept by the deciding wave
+        int hd = 0;                       // storage pair of pair 0 (ring form of B)
         int req = (SEQ && visits) ? kReqTotal : kReqInit;
         const int W = A.ftol_window;
         // batch descent (uniform): current batch, history count of batch p
@@ -469,9 +471,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         float ibK_v = 0.f, a2K_v = 0.f, bQ_v = 0.f;
 
         // relative decrease of the accepted energy over the last W iterations
-        // (lane w of ehist holds iteration w mod (W + 1)) at most ftol
-        auto decreased_too_little = [&](double Eacc) -> bool {
-            const int src = (it - W) % (W + 1);
+        // (lane w of ehist holds iteration w mod (W + 1); src: lane of
+        // iteration it - W) at most ftol
+        auto decreased_too_little = [&](double Eacc, int src) -> bool {
             const long long bits = __builtin_bit_cast(long long, ehist);
             const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
             const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
@@ -779,6 +781,50 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
+        // Whole-instance descent: B kept as a ring over the pair slots, so
+        // that an update writes only the rows and columns of the vectors it
+        // changes (g; on a push also the new s and y, stored over the
+        // evicted pair) straight from the slot totals; B[1] is unused.
+        // <a, b> of the new basis is the slot of the old vectors it stands
+        // for (a push renumbers old pair j + 1 as pair j).
+        auto gram_update_ring = [&](float tot, bool push, int lane) {
+            const int P = hd;                                     // storage pair of the new pair
+            if (push) hd = hd == kMM - 1 ? 0 : hd + 1;
+            const int pl = lane < kNB ? lane : kNB - 1;           // storage index of this lane's vector
+            const bool is_g = pl == kG, is_s = pl < kMM;
+            int j = (is_s ? pl : pl - kMM) - hd;                  // its pair index after the update
+            if (j < 0) j += kMM;
+            const bool newp = push && j == kMM - 1;               // the new s or y
+            const int jo = push ? j + 1 : j;                      // its pair index before
+            int sg;                                               // <gt, vector>
+            if (is_g) sg = sGG;
+            else if (newp) sg = is_s ? sScG : sYcG;
+            else sg = is_s ? sGS(jo) : sGY(jo);
+            const int ti = __builtin_bit_cast(int, tot);
+            const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sg, ti));
+            if (lane < kNB) {
+                sh.Bm[0][kG * kNB + pl] = vg;
+                sh.Bm[0][pl * kNB + kG] = vg;
+            }
+            if (push) {
+                int ss, sy;                                       // <sc, vector>, <yc, vector>
+                if (is_g) { ss = sScG; sy = sYcG; }
+                else if (newp) { ss = is_s ? sScSc : sScYc; sy = is_s ? sScYc : sYcYc; }
+                else { ss = is_s ? sSS(jo) : sSY(jo); sy = is_s ? sYS(jo) : sYY(jo); }
+                const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * ss, ti));
+                const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sy, ti));
+                if (lane < kNB) {
+                    sh.Bm[0][P * kNB + pl] = vs;
+                    sh.Bm[0][pl * kNB + P] = vs;
+                    sh.Bm[0][(kMM + P) * kNB + pl] = vy;
+                    sh.Bm[0][pl * kNB + kMM + P] = vy;
+                }
+                if (lane == 0) sh.rho[0][P] = 1.f / lane_value(tot, sScYc);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
         // Two-loop recursion on B. Lane l holds row l of B (the basis
         // s_0..s_9, y_0..y_9, g), so acc = (B c) for the current coefficient
         // vector c is one FMA per lane per step: q = g - sum_i a_i y_i gives
@@ -788,12 +834,22 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // lane-indexed in VGPRs (lane j: rho_j, a_j, the s_j coefficient; lane
         // 10 + j: rho_j and a_j again).  Returns g'p with p = -r; cs_v: the
         // coefficient of s_j at lane j; alph_v: a_j at lane j.
-        auto two_loop = [&](int lane, float &cs_out, float &alph_out, float &gam_out) -> float {
+        // hd: storage index of pair 0 when B is kept as a ring (pair j of
+        // the basis sits at storage pair (hd + j) mod 10), else 0.
+        auto two_loop = [&](int lane, int hd, float &cs_out, float &alph_out, float &gam_out) -> float {
+            // storage index of basis vector a
+            auto at = [&](int a) -> int {
+                if (a == kG) return kG;
+                const int base = a < kMM ? 0 : kMM;
+                int q = a - base + hd;
+                if (q >= kMM) q -= kMM;
+                return base + q;
+            };
             // lanes past row 20 read row 20 again: their values are never read
             float Bc[kNB];
-            const int lr = lane < kNB ? lane : kNB - 1;
+            const int lr = at(lane < kNB ? lane : kNB - 1);
 #pragma unroll
-            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = sh.Bm[cur][a2 * kNB + lr];
+            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = sh.Bm[cur][at(a2) * kNB + lr];
             const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
             const bool live = lane < 2 * kMM && jp >= kMM - k;
             const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
@@ -801,7 +857,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if constexpr (SEQ) {
                 rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
             } else {
-                rho_v = sh.rho[cur][jq];
+                rho_v = sh.rho[cur][at(jq)];
                 rho_v = live ? rho_v : 0.f;
             }
             float acc = Bc[kG];                                   // (B q)_l with q = g
@@ -1127,9 +1183,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     if (accept) {
                         fl = kDecAccept | (push ? kDecPush : 0);
-                        gram_update(tot, par, push, lane);
+                        gram_update_ring(tot, push, lane);
                         if (push) k = k + 1 > A.m ? A.m : k + 1;
-                        if (req == kReqTrial) ++it;
+                        if (req == kReqTrial) {
+                            ++it;
+                            itw = itw == W ? 0 : itw + 1;
+                        }
                         E = Et;
                         if (fp64) { E64o = so; E64t = st; }
                         // FP64 regime once either FP32 energy is small
@@ -1141,29 +1200,33 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     if (!(fl & (kDecNext | kDecStop))) {
                         // ---- top of an iteration: stop tests, direction
+                        // |g| <= g_tol and |g| finite, decided on |g|^2 (no
+                        // square root: g_tol_sq is the largest value whose
+                        // square root is at most g_tol)
                         const float gg = sh.Bm[cur][kG * kNB + kG];
-                        const float gn = sqrtf(fmaxf(gg, 0.f));
+                        const float gg0 = fmaxf(gg, 0.f);
                         const double Eacc = fp64 ? E64o : (double)E;
-                        if (!isfinite(E) || !isfinite(gn)) status = 6;
+                        const int itn = itw == W ? 0 : itw + 1;       // (it + 1) mod (W + 1)
+                        if (!isfinite(E) || !isfinite(gg0)) status = 6;
                         else if (fp64 && E64t < A.e_feasible) status = 1;
-                        else if (gn <= A.g_tol) status = 2;
-                        else if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) status = 3;
+                        else if (gg0 <= A.g_tol_sq) status = 2;
+                        else if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, itn)) status = 3;
                         else {
-                            if (lane == it % (W + 1)) ehist = Eacc;
+                            if (lane == itw) ehist = Eacc;
                             if (it >= A.max_iter) status = 5;
                         }
                         if (status != 0) {
                             fl |= kDecStop;
                         } else {
                             float cs_v, alph_v, gam;
-                            gp = two_loop(lane, cs_v, alph_v, gam);
+                            gp = two_loop(lane, hd, cs_v, alph_v, gam);
                             if (k > 0 && !(gp < 0.f)) {
                                 k = 0;
                                 gp = -gg;
                                 fl |= kDecSteepest;
                             }
                             if (k > 0) alpha = 1.f;
-                            else alpha = 1.f / fmaxf(1.f, gn);
+                            else alpha = 1.f / fmaxf(1.f, sqrtf(gg0));
                             h = 0;
                             req = kReqTrial;
                             if (lane < kMM) {
@@ -1273,7 +1336,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     if (!isfinite(E_tot)) { status = 6; break; }
                     if (E64t < A.e_feasible) { status = 1; break; }
                     if (it > 0 && gsum_prev <= A.g_tol) { status = 2; break; }
-                    if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) { status = 3; break; }
+                    if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1))) { status = 3; break; }
                     if (lane == it % (W + 1)) ehist = Eacc;
                     if (it > 0 && nvis > 0 && nstall == nvis) { status = 4; break; }
                     if (it >= A.max_iter) { status = 5; break; }
@@ -1408,7 +1471,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (!isfinite(E) || !isfinite(gn)) { status = 6; break; }
                 if (fp64 && E64t < A.e_feasible) { status = 1; break; }
                 if (gn <= A.g_tol) { status = 2; break; }
-                if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc)) { status = 3; break; }
+                if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1))) { status = 3; break; }
                 if (lane == it % (W + 1)) ehist = Eacc;
                 if (it >= A.max_iter) { status = 5; break; }
             }
@@ -1419,7 +1482,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             } else {
                 // ================= direction: two-loop recursion on B ===============
                 float cs_v, alph_v, gam;
-                gp = two_loop(lane, cs_v, alph_v, gam);
+                gp = two_loop(lane, 0, cs_v, alph_v, gam);
                 {
                     const float cy_v = -gam * alph_v;                 // coefficient of y_j at lane j
     #pragma unroll

@@ -28,6 +28,7 @@ hipError_t launch_verify(const int32_t *offset, const float *R, const double *R6
 struct DescentArgs {
     int m, max_iter, max_halvings, ftol_window;
     float c1, eps_curv, h_req, g_tol, ftol, rad;
+    float g_tol_sq;   // largest x with sqrtf(x) <= g_tol: the gradient test without a square root
     double c2, skin2, e_feasible, tau64;
     float lambda0;    // container adjustment: first penalty coefficient
     int rounds;       // container adjustment: minimisations, lambda halved after each
