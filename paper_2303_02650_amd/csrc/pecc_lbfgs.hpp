@@ -55,10 +55,9 @@ __device__ __forceinline__ void store_result(DescentResultDev *out, int b, const
     *reinterpret_cast<int2 *>(o + sizeof(DescentHead)) = make_int2(cell_evals, 0);
 }
 
-__device__ __forceinline__ float dot2(float2 a, float2 b) { return a.x * b.x + a.y * b.y; }
-
 // Value of reduction slot v summed over this thread's circles (v is a
-// constant after unrolling, so the branches fold away).
+// constant after unrolling, so the branches fold away): one FMA chain over
+// the circles' coordinates, started by a product.
 template <int CPT>
 __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], const float2 (&sc)[CPT],
                                             const float2 (&yc)[CPT],
@@ -67,25 +66,24 @@ __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], cons
 {
     if (v == sE) return e;
     if (v == sE1) return e1;
-    // the first circle's product starts the sum (adding it to 0 would cost
-    // an instruction per slot and round nothing)
-    float acc;
+    float acc = 0.f;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        float t;
-        if (v < kMM) t = dot2(gt[c], S[v][c]);
-        else if (v < 2 * kMM) t = dot2(gt[c], Y[v - kMM][c]);
-        else if (v < 3 * kMM - 1) t = dot2(sc[c], S[v - 2 * kMM + 1][c]);
-        else if (v < 4 * kMM - 2) t = dot2(sc[c], Y[v - (3 * kMM - 1) + 1][c]);
-        else if (v < 5 * kMM - 3) t = dot2(yc[c], S[v - (4 * kMM - 2) + 1][c]);
-        else if (v < 6 * kMM - 4) t = dot2(yc[c], Y[v - (5 * kMM - 3) + 1][c]);
-        else if (v == sGG) t = dot2(gt[c], gt[c]);
-        else if (v == sScSc) t = dot2(sc[c], sc[c]);
-        else if (v == sScYc) t = dot2(sc[c], yc[c]);
-        else if (v == sYcYc) t = dot2(yc[c], yc[c]);
-        else if (v == sScG) t = dot2(sc[c], gt[c]);
-        else t = dot2(yc[c], gt[c]);   // sYcG
-        acc = c == 0 ? t : acc + t;
+        float2 a, b;
+        if (v < kMM) { a = gt[c]; b = S[v][c]; }
+        else if (v < 2 * kMM) { a = gt[c]; b = Y[v - kMM][c]; }
+        else if (v < 3 * kMM - 1) { a = sc[c]; b = S[v - 2 * kMM + 1][c]; }
+        else if (v < 4 * kMM - 2) { a = sc[c]; b = Y[v - (3 * kMM - 1) + 1][c]; }
+        else if (v < 5 * kMM - 3) { a = yc[c]; b = S[v - (4 * kMM - 2) + 1][c]; }
+        else if (v < 6 * kMM - 4) { a = yc[c]; b = Y[v - (5 * kMM - 3) + 1][c]; }
+        else if (v == sGG) { a = gt[c]; b = gt[c]; }
+        else if (v == sScSc) { a = sc[c]; b = sc[c]; }
+        else if (v == sScYc) { a = sc[c]; b = yc[c]; }
+        else if (v == sYcYc) { a = yc[c]; b = yc[c]; }
+        else if (v == sScG) { a = sc[c]; b = gt[c]; }
+        else { a = yc[c]; b = gt[c]; }   // sYcG
+        acc = c == 0 ? a.x * b.x : fmaf(a.x, b.x, acc);
+        acc = fmaf(a.y, b.y, acc);
     }
     return acc;
 }
@@ -164,21 +162,34 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Slot held by lane L after wave_reduce_scatter (stages decided by lane bits
-// 3, 2, 1, 0, 4, 5 in this order).
-__device__ __forceinline__ int lane_slot(int L)
+// Slot held by lane L after wave_reduce_scatter: slot L.
+__device__ __forceinline__ int lane_slot(int L) { return L; }
+
+// Half swaps between two registers (gfx950 VALU permutes).  swap32: a keeps
+// its lanes 0-31 and receives b's lanes 0-31 in lanes 32-63; b receives a's
+// lanes 32-63 in lanes 0-31 and keeps its lanes 32-63.  swap16: the same on
+// 16-lane rows (a keeps rows 0, 2 and receives b's rows 0, 2 in rows 1, 3; b
+// receives a's rows 1, 3 and keeps its rows 1, 3).  Written as asm because
+// the builtins return one register twice in this compiler; the two wait
+// states cover a VALU write of either operand just before.
+__device__ __forceinline__ void swap32(float &a, float &b)
 {
-    return 32 * ((L >> 3) & 1) + 16 * ((L >> 2) & 1) + 8 * ((L >> 1) & 1) + 4 * (L & 1) +
-           2 * ((L >> 4) & 1) + ((L >> 5) & 1);
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap16(float &a, float &b)
+{
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
 }
 
 // Reduce-scatter of the 64 slot values over the wave: afterwards lane L
-// holds the wave sum of slot lane_slot(L).  Each stage pairs a lane with a
-// partner holding the same slot subset; the lane whose deciding bit is set
-// keeps the upper half.  Partners: stage 1 row mirror (bit 3), stage 2 half
-// mirror (bit 2), stage 3 xor 2, stage 4 xor 1 (all DPP), stage 5 xor 16,
-// stage 6 xor 32 (shuffles).  Slots are produced in the order the first three
-// stages consume them (u, u+8, ..., u+56) so only 8 values are live at once.
+// holds the wave sum of slot L.  Each stage halves the values per lane by
+// pairing slots that differ in one bit with lanes that differ in the same
+// bit: bit 5 and bit 4 by half swaps (slot q and q + 32 swapped between the
+// wave halves, then added: one swap and one add per pair), bits 3, 2, 1, 0
+// by DPP inside 16-lane rows (row mirror, half mirror, xor 2, xor 1; the lane
+// whose bit is set keeps the upper slot).  Slots are produced in groups of
+// eight (u + 8k, k = 0..7) that the first three stages consume, so only a
+// few values are live at once.
 template <int CPT>
 __device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[CPT],
                                                      const float2 (&sc)[CPT],
@@ -189,30 +200,36 @@ __device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[CPT],
 {
     const int lane = threadIdx.x & (kWave - 1);
     const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
-    const bool b0 = (lane & 1) != 0, b4 = (lane & 16) != 0, b5 = (lane & 32) != 0;
+    const bool b0 = (lane & 1) != 0;
     float h[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        float t1[4];
+        float w[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const float lo = slot_value(u + 8 * k, gt, sc, yc, S, Y, e, e1);
-            const float hi = slot_value(u + 8 * k + 32, gt, sc, yc, S, Y, e, e1);
-            t1[k] = (b3 ? hi : lo) + dpp<kDppRowMirror>(b3 ? lo : hi);
+            float lo = slot_value(u + 8 * k, gt, sc, yc, S, Y, e, e1);
+            float hi = slot_value(u + 8 * k + 32, gt, sc, yc, S, Y, e, e1);
+            swap32(lo, hi);
+            w[k] = lo + hi;            // lanes 0-31: slot u + 8k, lanes 32-63: + 32
         }
-        float t2[2];
+        float v[2];
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            t2[k] = (b2 ? t1[k + 2] : t1[k]) + dpp<kDppHalfMirror>(b2 ? t1[k] : t1[k + 2]);
-        h[u] = (b1 ? t2[1] : t2[0]) + dpp<kDppXor2>(b1 ? t2[0] : t2[1]);
+        for (int k = 0; k < 2; ++k) {
+            float lo = w[k], hi = w[k + 2];
+            swap16(lo, hi);
+            v[k] = lo + hi;            // rows 0, 2: slot of w[k]; rows 1, 3: + 16
+        }
+        h[u] = (b3 ? v[1] : v[0]) + dpp<kDppRowMirror>(b3 ? v[0] : v[1]);
         // keep the streaming order: the next group is not hoisted above here
         __builtin_amdgcn_sched_barrier(0);
     }
+    float t4[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) h[v] = (b0 ? h[v + 4] : h[v]) + dpp<kDppXor1>(b0 ? h[v] : h[v + 4]);
+    for (int v = 0; v < 4; ++v) t4[v] = (b2 ? h[v + 4] : h[v]) + dpp<kDppHalfMirror>(b2 ? h[v] : h[v + 4]);
+    float t2[2];
 #pragma unroll
-    for (int v = 0; v < 2; ++v) h[v] = (b4 ? h[v + 2] : h[v]) + __shfl_xor(b4 ? h[v] : h[v + 2], 16, kWave);
-    return (b5 ? h[1] : h[0]) + __shfl_xor(b5 ? h[0] : h[1], 32, kWave);
+    for (int v = 0; v < 2; ++v) t2[v] = (b1 ? t4[v + 2] : t4[v]) + dpp<kDppXor2>(b1 ? t4[v] : t4[v + 2]);
+    return (b0 ? t2[1] : t2[0]) + dpp<kDppXor1>(b0 ? t2[0] : t2[1]);
 }
 
 // Which vector basis index a of the updated basis is: 0 = an old basis
@@ -356,12 +373,13 @@ __device__ __forceinline__ float pair_term32s(float2 q, float2 pj, bool count_e,
     const bool ov = l2 < four_r2;
     const float il = __builtin_amdgcn_rsqf(fmaxf(l2, 1.17549435e-38f));
     const float d = ov ? two_r - l2 * il : 0.f;
-    e += count_e ? d * d : 0.f;
+    const float dc = count_e ? d : 0.f;       // the overlap if this term counts the pair
+    e = fmaf(dc, d, e);
     // the unit-circle energy (wave-uniform want_e1: only its caller's switch
     // into the FP64 regime reads it)
     if (want_e1) {
-        const float d1 = fmaxf(d - (two_r - 2.f), 0.f);
-        e1 += count_e ? d1 * d1 : 0.f;
+        const float d1 = fmaxf(dc - (two_r - 2.f), 0.f);
+        e1 = fmaf(d1, d1, e1);
     }
     const float kf = d * il;
     gx += kf * dx;
