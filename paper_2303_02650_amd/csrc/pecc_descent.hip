@@ -65,6 +65,13 @@ struct DescentShared {
     float dec_alpha;               // step length of the next trial
     float dec_gam;                 // gamma of the direction
     float coef[2][kMM];            // coefficients of s_j and y_j in the direction
+    // the constants of the decisions, read where used (kept in registers
+    // they would crowd out the loop's scalar state)
+    struct {
+        double tau64, e_feasible;
+        float c1, eps_curv, ftol, g_tol_sq;
+        int m, max_halvings, max_iter, pad;
+    } dk;
 };
 
 // Batch descent only: the saved Gram matrix of every batch, batch ids and
@@ -473,12 +480,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // relative decrease of the accepted energy over the last W iterations
         // (lane w of ehist holds iteration w mod (W + 1); src: lane of
         // iteration it - W) at most ftol
-        auto decreased_too_little = [&](double Eacc, int src) -> bool {
+        auto decreased_too_little = [&](double Eacc, int src, float ftol) -> bool {
             const long long bits = __builtin_bit_cast(long long, ehist);
             const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
             const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
             const double eold = __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-            return eold - Eacc <= (double)A.ftol * eold;
+            return eold - Eacc <= (double)ftol * eold;
         };
         // batch descent: batch bb's saved Gram matrix into B (every wave
         // writes the same values and reads back its own)
@@ -796,10 +803,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (j < 0) j += kMM;
             const bool newp = push && j == kMM - 1;               // the new s or y
             const int jo = push ? j + 1 : j;                      // its pair index before
-            int sg;                                               // <gt, vector>
-            if (is_g) sg = sGG;
-            else if (newp) sg = is_s ? sScG : sYcG;
-            else sg = is_s ? sGS(jo) : sGY(jo);
+            // slot indices as selects (no branches): <gt, vector>
+            const int sg = is_g ? sGG : newp ? (is_s ? sScG : sYcG) : (is_s ? sGS(jo) : sGY(jo));
             const int ti = __builtin_bit_cast(int, tot);
             const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sg, ti));
             if (lane < kNB) {
@@ -807,10 +812,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 sh.Bm[0][pl * kNB + kG] = vg;
             }
             if (push) {
-                int ss, sy;                                       // <sc, vector>, <yc, vector>
-                if (is_g) { ss = sScG; sy = sYcG; }
-                else if (newp) { ss = is_s ? sScSc : sScYc; sy = is_s ? sScYc : sYcYc; }
-                else { ss = is_s ? sSS(jo) : sSY(jo); sy = is_s ? sYS(jo) : sYY(jo); }
+                // <sc, vector>, <yc, vector> (sSS(jo) etc. are linear in jo)
+                const int ss = is_g ? sScG : newp ? (is_s ? sScSc : sScYc) : (is_s ? sSS(jo) : sSY(jo));
+                const int sy = is_g ? sYcG : newp ? (is_s ? sScYc : sYcYc) : (is_s ? sYS(jo) : sYY(jo));
                 const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * ss, ti));
                 const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sy, ti));
                 if (lane < kNB) {
@@ -893,7 +897,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
         for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
-        if (tid == 0) { sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0; }
+        if (tid == 0) {
+            sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0;
+            sh.dk.tau64 = A.tau64; sh.dk.e_feasible = A.e_feasible;
+            sh.dk.c1 = A.c1; sh.dk.eps_curv = A.eps_curv; sh.dk.ftol = A.ftol; sh.dk.g_tol_sq = A.g_tol_sq;
+            sh.dk.m = A.m; sh.dk.max_halvings = A.max_halvings; sh.dk.max_iter = A.max_iter; sh.dk.pad = 0;
+        }
 
         // container adjustment state (uniform): radius, its gradient and
         // search components, penalty coefficient; hR_v: radius component of
@@ -1145,6 +1154,19 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 // would share each SIMD with a copy of itself.  The outcome
                 // reaches the other waves through LDS behind one barrier.
                 if (wv == 0) {
+                    auto ufl = [](float v) { return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v))); };
+                    auto udb = [](double v) {
+                        const long long b = __builtin_bit_cast(long long, v);
+                        const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+                        const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+                        return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+                    };
+                    const float c1 = ufl(sh.dk.c1), eps_curv = ufl(sh.dk.eps_curv), ftol = ufl(sh.dk.ftol);
+                    const float g_tol_sq = ufl(sh.dk.g_tol_sq);
+                    const double tau64 = udb(sh.dk.tau64), e_feasible = udb(sh.dk.e_feasible);
+                    const int mm = __builtin_amdgcn_readfirstlane(sh.dk.m);
+                    const int max_halvings = __builtin_amdgcn_readfirstlane(sh.dk.max_halvings);
+                    const int max_iter = __builtin_amdgcn_readfirstlane(sh.dk.max_iter);
                     float tot = 0.f;
 #pragma unroll
                     for (int w = 0; w < kDW; ++w) tot += sh.red[par][w][lane];
@@ -1164,15 +1186,15 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     int fl = 0;
                     bool accept = false, push = false;
                     if (req == kReqTrial) {
-                        const bool ok = fp64 ? so <= E64o + (double)A.c1 * (double)alpha * (double)gp
-                                             : Et <= E + A.c1 * alpha * gp;
+                        const bool ok = fp64 ? so <= E64o + (double)c1 * (double)alpha * (double)gp
+                                             : Et <= E + c1 * alpha * gp;
                         if (ok) {
                             accept = true;
                             const float sy = lane_value(tot, sScYc), yy = lane_value(tot, sYcYc);
-                            push = sy > A.eps_curv * yy;
+                            push = sy > eps_curv * yy;
                         } else {
                             alpha *= 0.5f;
-                            if (++h > A.max_halvings) { status = 4; fl = kDecStop; }   // STALLED
+                            if (++h > max_halvings) { status = 4; fl = kDecStop; }   // STALLED
                             else fl = kDecNext;
                         }
                     } else if (req == kReqInit) {
@@ -1184,7 +1206,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     if (accept) {
                         fl = kDecAccept | (push ? kDecPush : 0);
                         gram_update_ring(tot, push, lane);
-                        if (push) k = k + 1 > A.m ? A.m : k + 1;
+                        if (push) k = k + 1 > mm ? mm : k + 1;
                         if (req == kReqTrial) {
                             ++it;
                             itw = itw == W ? 0 : itw + 1;
@@ -1192,7 +1214,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         E = Et;
                         if (fp64) { E64o = so; E64t = st; }
                         // FP64 regime once either FP32 energy is small
-                        if (!fp64 && A.tau64 > 0.0 && (double)fminf(E, E1t) < A.tau64) {
+                        if (!fp64 && tau64 > 0.0 && (double)fminf(E, E1t) < tau64) {
                             fp64 = true;
                             req = kReqFp64;          // FP64 energies of x before going on
                             fl |= kDecNext;
@@ -1202,24 +1224,26 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         // ---- top of an iteration: stop tests, direction
                         // |g| <= g_tol and |g| finite, decided on |g|^2 (no
                         // square root: g_tol_sq is the largest value whose
-                        // square root is at most g_tol)
-                        const float gg = sh.Bm[cur][kG * kNB + kG];
+                        // square root is at most g_tol).  The tests are
+                        // selects and the two-loop runs before their outcome
+                        // is looked at, so both chains share the issue slots.
+                        const float gg = accept ? lane_value(tot, sGG) : sh.Bm[0][kG * kNB + kG];
                         const float gg0 = fmaxf(gg, 0.f);
                         const double Eacc = fp64 ? E64o : (double)E;
                         const int itn = itw == W ? 0 : itw + 1;       // (it + 1) mod (W + 1)
-                        if (!isfinite(E) || !isfinite(gg0)) status = 6;
-                        else if (fp64 && E64t < A.e_feasible) status = 1;
-                        else if (gg0 <= A.g_tol_sq) status = 2;
-                        else if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, itn)) status = 3;
-                        else {
-                            if (lane == itw) ehist = Eacc;
-                            if (it >= A.max_iter) status = 5;
-                        }
+                        const bool dtl = ftol > 0.f && it >= W && decreased_too_little(Eacc, itn, ftol);
+                        status = (!isfinite(E) || !isfinite(gg0)) ? 6
+                               : (fp64 && E64t < e_feasible)      ? 1
+                               : gg0 <= g_tol_sq                   ? 2
+                               : dtl                               ? 3
+                               : it >= max_iter                    ? 5 : 0;
+                        if (lane == itw) ehist = Eacc;                // read above before written
+                        float cs_v, alph_v, gam;
+                        const float gpv = two_loop(lane, hd, cs_v, alph_v, gam);
                         if (status != 0) {
                             fl |= kDecStop;
                         } else {
-                            float cs_v, alph_v, gam;
-                            gp = two_loop(lane, hd, cs_v, alph_v, gam);
+                            gp = gpv;
                             if (k > 0 && !(gp < 0.f)) {
                                 k = 0;
                                 gp = -gg;
@@ -1336,7 +1360,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     if (!isfinite(E_tot)) { status = 6; break; }
                     if (E64t < A.e_feasible) { status = 1; break; }
                     if (it > 0 && gsum_prev <= A.g_tol) { status = 2; break; }
-                    if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1))) { status = 3; break; }
+                    if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1), A.ftol)) { status = 3; break; }
                     if (lane == it % (W + 1)) ehist = Eacc;
                     if (it > 0 && nvis > 0 && nstall == nvis) { status = 4; break; }
                     if (it >= A.max_iter) { status = 5; break; }
@@ -1471,7 +1495,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 if (!isfinite(E) || !isfinite(gn)) { status = 6; break; }
                 if (fp64 && E64t < A.e_feasible) { status = 1; break; }
                 if (gn <= A.g_tol) { status = 2; break; }
-                if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1))) { status = 3; break; }
+                if (A.ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1), A.ftol)) { status = 3; break; }
                 if (lane == it % (W + 1)) ehist = Eacc;
                 if (it >= A.max_iter) { status = 5; break; }
             }
