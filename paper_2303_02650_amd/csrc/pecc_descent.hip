@@ -45,7 +45,7 @@ struct DescentShared {
     int cell_start[kMaxCells + 1];
     uint16_t cell_circ[kMaxN];
     uint16_t slot_tmp[kMaxN];
-    uint16_t list[ELL][kMaxN];     // slot-major: lanes read consecutive entries
+    uint16_t list[ELL][kMaxN];     // slot-major: lanes read consecutive entries; byte offsets into pos
     uint8_t  list_n[kMaxN];
     float red[2][kDW][kWave];
     double red64[2][kDW][2];
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     for_each_candidate(i, x[c], grid, sh.cell_start, sh.cell_circ, [&](int j) {
                         if (near_cut(x[c], sh.pos[j], c2lo, c2hi, A.c2)) {
                             bool found = false;
-                            for (int t = 0; t < old; ++t) found = found || sh.list[t][i] == j;
+                            for (int t = 0; t < old; ++t) found = found || sh.list[t][i] == j * (int)sizeof(float2);
                             if (!found) diff = 1;
                             ++m;
                         }
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             for (int t = a; t < z; ++t) {
                                 const int j = sh.cell_circ[t];
                                 if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) {
-                                    if (m < ELL) sh.list[m][i] = (uint16_t)j;
+                                    if (m < ELL) sh.list[m][i] = (uint16_t)(j * (int)sizeof(float2));
                                     ++m;
                                     up += j > i;
                                 }
@@ -1040,36 +1040,48 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     mc[c] = (act[c] && inb[c]) ? sh.list_n[tid + c * kDB] : 0;
                     mm = mc[c] > mm ? mc[c] : mm;
                 }
-                for (int t = 0; t < mm; ++t) {
-                    int jv[kCPT];
-                    float2 pj[kCPT];
+                // one copy of the loop per (unit-circle energy, FP64 terms)
+                // regime, so neither costs instructions where it is off
+                auto sweep = [&](auto e1_tag, auto w64_tag) {
+                    constexpr bool kE1 = decltype(e1_tag)::value, kW64 = decltype(w64_tag)::value;
+                    for (int t = 0; t < mm; ++t) {
+                        int jv[kCPT];                  // byte offsets into pos
+                        float2 pj[kCPT];
 #pragma unroll
-                    for (int c = 0; c < kCPT; ++c) {
-                        const int i = tid + c * kDB;
-                        jv[c] = t < mc[c] ? (int)sh.list[t][i] : i;
-                    }
+                        for (int c = 0; c < kCPT; ++c) {
+                            const int i = tid + c * kDB;
+                            jv[c] = t < mc[c] ? (int)sh.list[t][i] : i * (int)sizeof(float2);
+                        }
 #pragma unroll
-                    for (int c = 0; c < kCPT; ++c) pj[c] = sh.pos[jv[c]];
+                        for (int c = 0; c < kCPT; ++c)
+                            pj[c] = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(sh.pos) + jv[c]);
 #pragma unroll
-                    for (int c = 0; c < kCPT; ++c) {
-                        const int i = tid + c * kDB;
-                        if (t < mc[c]) {
-                            const int j = jv[c];
-                            const float2 q = xt[c];
-                            // each pair once: from its lower index, or (batch
-                            // energy, Eq. 7) from the batch's end
-                            bool hf = j > i;
-                            if constexpr (SEQ) if (masked) hf = hf || sq.bat[j] != cb;
-                            float l2;
-                            const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
-                                                          ecA[c], e1cA[c], gxA[c], gyA[c], l2,
-                                                          want_e1);
-                            // FP64 energies only where FP32 sees (nearly) an overlap:
-                            // outside a 1e-5 band the FP64 terms are zero
-                            if (want64 && hf && l2 < four_r2_band)
-                                pair_term64s(q, pj[c], l2 * il, il, two_r64, four_r2_64, eocA[c], etcA[c]);
+                        for (int c = 0; c < kCPT; ++c) {
+                            const int i = tid + c * kDB;
+                            if (t < mc[c]) {
+                                const int jb = jv[c];
+                                const float2 q = xt[c];
+                                // each pair once: from its lower index, or (batch
+                                // energy, Eq. 7) from the batch's end
+                                bool hf = jb > i * (int)sizeof(float2);
+                                if constexpr (SEQ) if (masked) hf = hf || sq.bat[jb / (int)sizeof(float2)] != cb;
+                                float l2;
+                                const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
+                                                              ecA[c], e1cA[c], gxA[c], gyA[c], l2, kE1);
+                                // FP64 energies only where FP32 sees (nearly) an overlap:
+                                // outside a 1e-5 band the FP64 terms are zero
+                                if (kW64 && hf && l2 < four_r2_band)
+                                    pair_term64s(q, pj[c], l2 * il, il, two_r64, four_r2_64, eocA[c], etcA[c]);
+                            }
                         }
                     }
+                };
+                using T_ = std::true_type;
+                using F_ = std::false_type;
+                if (want64) {
+                    if (want_e1) sweep(T_{}, T_{}); else sweep(F_{}, T_{});
+                } else {
+                    if (want_e1) sweep(T_{}, F_{}); else sweep(F_{}, F_{});
                 }
             }
 #pragma unroll

@@ -371,7 +371,9 @@ __device__ __forceinline__ float pair_term32s(float2 q, float2 pj, bool count_e,
     const float dx = q.x - pj.x, dy = q.y - pj.y;
     const float l2 = dx * dx + dy * dy;
     const bool ov = l2 < four_r2;
-    const float il = __builtin_amdgcn_rsqf(fmaxf(l2, 1.17549435e-38f));
+    // + FLT_MIN: a finite inverse for coincident centres; a no-op (exact)
+    // for any l2 above 2^-100
+    const float il = __builtin_amdgcn_rsqf(l2 + 1.17549435e-38f);
     const float d = ov ? two_r - l2 * il : 0.f;
     const float dc = count_e ? d : 0.f;       // the overlap if this term counts the pair
     e = fmaf(dc, d, e);
