@@ -197,16 +197,19 @@ __global__ __launch_bounds__(kBuildBlock) void build_fill_kernel(
 // list costs 4 bytes per pair).  Each thread owns circles and sums their
 // pair terms in list order: no atomics.  One workgroup of 256 threads per
 // instance; positions (8 KB) and the instance's list segment (when it fits,
-// 6128 entries) are staged in LDS with coalesced streaming (non-temporal)
-// 16-byte loads, the segment held as 16-bit local indices, so global memory
-// sees each byte once, and the gradient leaves with streaming 8-byte stores.
-// The LDS footprint (20,480 bytes) lets eight workgroups (32 waves) stay
-// resident per CU, overlapping one instance's loads with another's
-// arithmetic, and each thread walks the lists of two circles at once so
-// that their LDS reads overlap.
+// up to 6123 entries) are staged in LDS with coalesced streaming
+// (non-temporal) 16-byte loads, the segment held as 16-bit byte offsets into
+// the staged positions, so global memory sees each byte once, and the
+// gradient leaves with streaming 8-byte stores.  An entry past a row's end
+// reads a sentinel that points at a position far outside every container,
+// so the pair loop needs no tests of its own.  The LDS footprint (20,464
+// bytes) lets eight workgroups (32 waves) stay resident per CU, overlapping
+// one instance's loads with another's arithmetic, and each thread walks the
+// lists of two circles at once so that their LDS reads overlap.
 // ---------------------------------------------------------------------------
 constexpr int kSweepBlock = 256;
-constexpr int kColLds = 6128;   // 8192 + 2 * 6128 + 16 bytes of LDS fit 8 workgroups per CU
+constexpr int kColLds = 6124;   // 8200 + 2 * 6124 + 16 bytes of LDS fit 8 workgroups per CU
+constexpr uint16_t kFarOff = kMaxN * sizeof(float2);   // byte offset of the far position
 
 template <typename Idx>
 __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
     // entries per 16-byte load; a local index needs no offset
     constexpr int kIV = 16 / (int)sizeof(Idx);
     constexpr bool kLocal = sizeof(Idx) == 2;
-    __shared__ float2 pos[kMaxN];
+    __shared__ float2 pos[kMaxN + 1];         // + the far position
     __shared__ uint16_t col_s[kColLds];
     __shared__ float sum_tmp[kSweepBlock / kWave];
 
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
         if (threadIdx.x == 0) energy[b] = __builtin_nanf("");
         return;
     }
-    const bool staged = len <= kColLds;
+    const bool staged = len < kColLds;         // room for the sentinel
     // One batch of streaming loads per thread -- positions as float4 where
     // the instance start is 16-byte aligned, the list segment as int4 -- all
     // issued before the first is used, so the workgroup waits for memory
@@ -284,9 +287,11 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
         const int i = threadIdx.x + c * kSweepBlock + 1;
         rw1[c] = row[off + (i < n ? i : n)];
     }
+    // an entry as the byte offset of its position; one outside the
+    // instance as the far position (a pair that does not overlap)
     auto put = [&](int k, int v) {
         const int jj = kLocal ? v : v - off;
-        col_s[k] = (unsigned)jj < (unsigned)n ? (uint16_t)jj : (uint16_t)0xFFFF;
+        col_s[k] = (unsigned)jj < (unsigned)n ? (uint16_t)(jj * (int)sizeof(float2)) : kFarOff;
     };
     if (!pos_al) {
         stage_positions<kSweepBlock>(xy, off, n, pos);
@@ -294,6 +299,10 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
         pos[n - 1] = reinterpret_cast<const float2 *>(xy)[off + n - 1];
     }
     if (staged) {
+        if (threadIdx.x == 0) {
+            col_s[len] = kFarOff;                         // sentinel past the last row
+            pos[kMaxN] = make_float2(1e18f, 1e18f);       // squared distances stay finite
+        }
         if ((int)threadIdx.x < head) put(threadIdx.x, col[r0 + threadIdx.x]);
         for (int k = head + kIV * nv + threadIdx.x; k < len; k += kSweepBlock) put(k, col[r0 + k]);
     }
@@ -347,44 +356,46 @@ __global__ __launch_bounds__(kSweepBlock) void energy_grad_full_kernel(
       const int span = max(zA[0] - aA[0], zA[1] - aA[1]);
       const float2 piA[2] = {pos[i0], i0 + kSweepBlock < n ? pos[i0 + kSweepBlock] : make_float2(0.f, 0.f)};
       // one pass over the rows, branch-free: an entry past its row or
-      // outside the instance reads index 0xFFFF and is taken as a pair
-      // that does not overlap.  Per pair side: kf' = d / l (the factor -2
-      // of the gradient term is applied to the sums at the end, exactly),
-      // and d^2 of every side (each pair counted twice, halved at the end);
-      // 1/l from max(l^2, FLT_MIN), so coincident centres (l = 0, dx = dy
-      // = 0) give d = 2 rad and no gradient without a test of their own.
+      // outside the instance is the far position, a pair that does not
+      // overlap.  Per pair side: kf' = d / l (the factor -2 of the gradient
+      // term is applied to the sums at the end, exactly), and d^2 of every
+      // side (each pair counted twice, halved at the end); 1/l from
+      // l^2 + FLT_MIN (exactly l^2 above 2^-100), so coincident centres (l =
+      // 0, dx = dy = 0) give d = 2 rad and no gradient without a test of
+      // their own.
       auto rows_pass = [&](auto staged_c) {
           constexpr bool ST = decltype(staged_c)::value;
 #pragma unroll 1
           for (int t = 0; t < span; ++t) {
-              int jA[2];
               float2 pjA[2];
+              bool realA[2];
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                   const int k = aA[h] + t;
-                  int j;
                   if constexpr (ST) {
-                      j = col_s[k < kColLds ? k : 0];
+                      // past the row: the sentinel at col_s[len]
+                      const int off8 = col_s[k < zA[h] ? k : len];
+                      pjA[h] = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(pos) + off8);
+                      realA[h] = true;
                   } else {
-                      j = 0xFFFF;
+                      int j = 0xFFFF;
                       if (k < zA[h]) j = kLocal ? (int)col[r0 + k] : col[r0 + k] - off;
+                      realA[h] = (unsigned)j < (unsigned)n;
+                      pjA[h] = pos[realA[h] ? j : 0];
                   }
-                  jA[h] = k < zA[h] ? j : 0xFFFF;
               }
-#pragma unroll
-              for (int h = 0; h < 2; ++h) pjA[h] = pos[(unsigned)jA[h] < (unsigned)n ? jA[h] : 0];
 #pragma unroll
               for (int h = 0; h < 2; ++h) {
                   const float2 pi = piA[h], pj = pjA[h];
                   const float dx = pi.x - pj.x, dy = pi.y - pj.y;
                   const float l2r = dx * dx + dy * dy;
-                  const float l2 = (unsigned)jA[h] < (unsigned)n ? l2r : four_r2;
-                  const float il = __builtin_amdgcn_rsqf(fmaxf(l2, 1.17549435e-38f));
+                  const float l2 = ST || realA[h] ? l2r : four_r2;
+                  const float il = __builtin_amdgcn_rsqf(l2 + 1.17549435e-38f);
                   const float d = l2 < four_r2 ? two_r - l2 * il : 0.f;
-                  eiA[h] += d * d;
+                  eiA[h] = fmaf(d, d, eiA[h]);
                   const float kf = d * il;
-                  gxA[h] += kf * dx;
-                  gyA[h] += kf * dy;
+                  gxA[h] = fmaf(kf, dx, gxA[h]);
+                  gyA[h] = fmaf(kf, dy, gyA[h]);
               }
           }
       };
