@@ -39,9 +39,22 @@ constexpr int kEllSeq = 32;               // ... in the batch descent (l_cut up 
 
 enum : int { kModeWhole = 0, kModeAdj = 1, kModeSeq = 2, kModeDense = 3 };
 
+// Byte offset (into the position array) of the far point that pads every
+// neighbor list up to the longest list of its wave: a pair with it has no
+// overlap, so its terms add exact zeros and the list loop needs no test.
+constexpr int kFarOff = kMaxN * (int)sizeof(float2);
+constexpr float kFarCoord = 3.0e18f;      // (3e18)^2 * 2 is finite in FP32
+
+// Whole-instance descent: row length of the Gram ring in LDS.  Row r (the
+// basis vector in storage slot r: s 0..9, y 10..19, g 20) holds the s
+// storage slots twice (0..9, 10..19), the y slots twice (20..29, 30..39)
+// and g (40), so that the row of any basis vector read in pair order (pair
+// j at storage (hd + j) mod 10) is contiguous from offset hd.
+constexpr int kRS = 4 * kMM + 1;
+
 template <int ELL>
 struct DescentShared {
-    float2 pos[kMaxN];
+    float2 pos[kMaxN + 1];         // pos[kMaxN]: the far point
     int cell_start[kMaxCells + 1];
     uint16_t cell_circ[kMaxN];
     uint16_t slot_tmp[kMaxN];
@@ -50,6 +63,8 @@ struct DescentShared {
     float red[2][kDW][kWave];
     double red64[2][kDW][2];
     float Bm[2][kNB * kNB];
+    float Bring[kNB * kRS];        // whole-instance descent: Gram ring, rows as above
+    uint32_t bperm[kWave];         // source slots of the Gram update per lane (byte addresses)
     float tot_s[2][kWave];
     float rho[2][kMM];             // 1 / s_j'y_j of the Gram buffer of the same index
     uint16_t bsrc[2][kNB * kNB];   // Gram update sources, see gram_source
@@ -309,6 +324,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int q = tid; q < 2 * kNB * kNB; q += kDB)
         sh.bsrc[q / (kNB * kNB)][q % (kNB * kNB)] = gram_source(q % (kNB * kNB), q >= kNB * kNB);
+    if constexpr (SOLO)
+        if (tid < kWave) sh.bperm[tid] = gram_perm_bytes(tid);
     const float c2lo = (float)(A.c2 * (1.0 - 1e-5)), c2hi = (float)(A.c2 * (1.0 + 1e-5));
 
     for (;;) {
@@ -788,46 +805,17 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
-        // Whole-instance descent: B kept as a ring over the pair slots, so
-        // that an update writes only the rows and columns of the vectors it
-        // changes (g; on a push also the new s and y, stored over the
-        // evicted pair) straight from the slot totals; B[1] is unused.
-        // <a, b> of the new basis is the slot of the old vectors it stands
-        // for (a push renumbers old pair j + 1 as pair j).
-        auto gram_update_ring = [&](float tot, bool push, int lane) {
-            const int P = hd;                                     // storage pair of the new pair
-            if (push) hd = hd == kMM - 1 ? 0 : hd + 1;
-            const int pl = lane < kNB ? lane : kNB - 1;           // storage index of this lane's vector
-            const bool is_g = pl == kG, is_s = pl < kMM;
-            int j = (is_s ? pl : pl - kMM) - hd;                  // its pair index after the update
-            if (j < 0) j += kMM;
-            const bool newp = push && j == kMM - 1;               // the new s or y
-            const int jo = push ? j + 1 : j;                      // its pair index before
-            // slot indices as selects (no branches): <gt, vector>
-            const int sg = is_g ? sGG : newp ? (is_s ? sScG : sYcG) : (is_s ? sGS(jo) : sGY(jo));
-            const int ti = __builtin_bit_cast(int, tot);
-            const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sg, ti));
-            if (lane < kNB) {
-                sh.Bm[0][kG * kNB + pl] = vg;
-                sh.Bm[0][pl * kNB + kG] = vg;
-            }
-            if (push) {
-                // <sc, vector>, <yc, vector> (sSS(jo) etc. are linear in jo)
-                const int ss = is_g ? sScG : newp ? (is_s ? sScSc : sScYc) : (is_s ? sSS(jo) : sSY(jo));
-                const int sy = is_g ? sYcG : newp ? (is_s ? sScYc : sYcYc) : (is_s ? sYS(jo) : sYY(jo));
-                const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * ss, ti));
-                const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * sy, ti));
-                if (lane < kNB) {
-                    sh.Bm[0][P * kNB + pl] = vs;
-                    sh.Bm[0][pl * kNB + P] = vs;
-                    sh.Bm[0][(kMM + P) * kNB + pl] = vy;
-                    sh.Bm[0][pl * kNB + kMM + P] = vy;
-                }
-                if (lane == 0) sh.rho[0][P] = 1.f / lane_value(tot, sScYc);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // Whole-instance descent: B is kept as a ring over the pair slots
+        // (pair j of the basis at storage pair (hd + j) mod 10), so that an
+        // update writes only the rows and columns of the vectors it changes
+        // (g; on a push also the new s and y, stored over the evicted pair)
+        // straight from the slot totals.  Storage index of basis vector a:
+        auto ring_at = [&](int a) -> int {
+            if (a == kG) return kG;
+            const int base = a < kMM ? 0 : kMM;
+            int q = a - base + hd;
+            if (q >= kMM) q -= kMM;
+            return base + q;
         };
         // Two-loop recursion on B. Lane l holds row l of B (the basis
         // s_0..s_9, y_0..y_9, g), so acc = (B c) for the current coefficient
@@ -838,32 +826,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // lane-indexed in VGPRs (lane j: rho_j, a_j, the s_j coefficient; lane
         // 10 + j: rho_j and a_j again).  Returns g'p with p = -r; cs_v: the
         // coefficient of s_j at lane j; alph_v: a_j at lane j.
-        // hd: storage index of pair 0 when B is kept as a ring (pair j of
-        // the basis sits at storage pair (hd + j) mod 10), else 0.
-        auto two_loop = [&](int lane, int hd, float &cs_out, float &alph_out, float &gam_out) -> float {
-            // storage index of basis vector a
-            auto at = [&](int a) -> int {
-                if (a == kG) return kG;
-                const int base = a < kMM ? 0 : kMM;
-                int q = a - base + hd;
-                if (q >= kMM) q -= kMM;
-                return base + q;
-            };
-            // lanes past row 20 read row 20 again: their values are never read
-            float Bc[kNB];
-            const int lr = at(lane < kNB ? lane : kNB - 1);
-#pragma unroll
-            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = sh.Bm[cur][at(a2) * kNB + lr];
+        auto two_loop_core = [&](int lane, const float (&Bc)[kNB], float rho_v, float &cs_out,
+                                 float &alph_out, float &gam_out) -> float {
             const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
-            const bool live = lane < 2 * kMM && jp >= kMM - k;
-            const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
-            float rho_v;
-            if constexpr (SEQ) {
-                rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
-            } else {
-                rho_v = sh.rho[cur][at(jq)];
-                rho_v = live ? rho_v : 0.f;
-            }
             float acc = Bc[kG];                                   // (B q)_l with q = g
             float alph_v = 0.f;                                   // a_j at lanes j and 10 + j
             // every pair slot in straight-line code: a slot without a pair
@@ -894,11 +859,42 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             gam_out = gam;
             return -lane_value(acc, kG);                          // g'p = -g'r
         };
+        // Loads this lane's row of B (pair order through the storage map at,
+        // double-buffered form: hd = 0) and rho, then the recursion above.
+        auto two_loop = [&](int lane, int hd, float &cs_out, float &alph_out, float &gam_out) -> float {
+            // storage index of basis vector a
+            auto at = [&](int a) -> int {
+                if (a == kG) return kG;
+                const int base = a < kMM ? 0 : kMM;
+                int q = a - base + hd;
+                if (q >= kMM) q -= kMM;
+                return base + q;
+            };
+            // lanes past row 20 read row 20 again: their values are never read
+            float Bc[kNB];
+            const int lr = at(lane < kNB ? lane : kNB - 1);
+#pragma unroll
+            for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = sh.Bm[cur][at(a2) * kNB + lr];
+            const int jp = lane < kMM ? lane : lane - kMM;        // pair index of lanes 0..19
+            const bool live = lane < 2 * kMM && jp >= kMM - k;
+            const int jq = lane < 2 * kMM ? jp : 0;               // in-range index on every lane
+            float rho_v;
+            if constexpr (SEQ) {
+                rho_v = live ? 1.f / sh.Bm[cur][jq * kNB + kMM + jq] : 0.f;
+            } else {
+                rho_v = sh.rho[cur][at(jq)];
+                rho_v = live ? rho_v : 0.f;
+            }
+            return two_loop_core(lane, Bc, rho_v, cs_out, alph_out, gam_out);
+        };
 
         for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
+        if constexpr (SOLO)
+            for (int q = tid; q < kNB * kRS; q += kDB) sh.Bring[q] = 0.f;
         for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
         if (tid == 0) {
             sh.flag[0] = 1; sh.flag[1] = 0; sh.cell_evals = 0;
+            sh.pos[kMaxN] = make_float2(kFarCoord, kFarCoord);
             sh.dk.tau64 = A.tau64; sh.dk.e_feasible = A.e_feasible;
             sh.dk.c1 = A.c1; sh.dk.eps_curv = A.eps_curv; sh.dk.ftol = A.ftol; sh.dk.g_tol_sq = A.g_tol_sq;
             sh.dk.m = A.m; sh.dk.max_halvings = A.max_halvings; sh.dk.max_iter = A.max_iter; sh.dk.pad = 0;
@@ -1007,6 +1003,21 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         xr[c] = xt[c];
                     }
                 }
+                // pad every list with the far point up to the longest list
+                // of the wave (the sweep's trip count; circles past n count
+                // as empty lists)
+                {
+                    int mlen[kCPT], mw = 0;
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) {
+                        mlen[c] = act[c] ? (int)sh.list_n[tid + c * kDB] : 0;
+                        mw = mlen[c] > mw ? mlen[c] : mw;
+                    }
+                    mw = wave_max_dpp(mw);
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c)
+                        for (int t = mlen[c]; t < mw; ++t) sh.list[t][tid + c * kDB] = (uint16_t)kFarOff;
+                }
                 ++rebuilds;
                 __syncthreads();
                 overflow = sh.over != 0;
@@ -1033,24 +1044,37 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 eocA[c] = etcA[c] = 0.0;
             }
             if (!overflow) {
-                int mc[kCPT];
+                // trip count: the longest swept list of the wave (uniform);
+                // shorter lists are padded with the far point
+                bool use[kCPT];
                 int mm = 0;
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
-                    mc[c] = (act[c] && inb[c]) ? sh.list_n[tid + c * kDB] : 0;
-                    mm = mc[c] > mm ? mc[c] : mm;
+                    use[c] = act[c] && inb[c];
+                    const int mcc = use[c] ? (int)sh.list_n[tid + c * kDB] : 0;
+                    mm = mcc > mm ? mcc : mm;
                 }
+                mm = wave_max_dpp(mm);
                 // one copy of the loop per (unit-circle energy, FP64 terms)
-                // regime, so neither costs instructions where it is off
+                // regime, so neither costs instructions where it is off.  The
+                // list entries of slot t + 1 are read while slot t is summed,
+                // so a slot waits for one LDS read (its partners) instead of
+                // two in a chain.
                 auto sweep = [&](auto e1_tag, auto w64_tag) {
                     constexpr bool kE1 = decltype(e1_tag)::value, kW64 = decltype(w64_tag)::value;
+                    int jn[kCPT];                      // byte offsets into pos, next slot
+#pragma unroll
+                    for (int c = 0; c < kCPT; ++c) jn[c] = sh.list[0][tid + c * kDB];
                     for (int t = 0; t < mm; ++t) {
-                        int jv[kCPT];                  // byte offsets into pos
+                        int jv[kCPT];
                         float2 pj[kCPT];
+                        const int tn = t + 1 < ELL ? t + 1 : ELL - 1;
 #pragma unroll
                         for (int c = 0; c < kCPT; ++c) {
-                            const int i = tid + c * kDB;
-                            jv[c] = t < mc[c] ? (int)sh.list[t][i] : i * (int)sizeof(float2);
+                            jv[c] = jn[c];
+                            // batch visit: circles outside the batch take the far point
+                            if constexpr (SEQ) if (masked) jv[c] = use[c] ? jv[c] : kFarOff;
+                            jn[c] = sh.list[tn][tid + c * kDB];
                         }
 #pragma unroll
                         for (int c = 0; c < kCPT; ++c)
@@ -1058,21 +1082,22 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
                         for (int c = 0; c < kCPT; ++c) {
                             const int i = tid + c * kDB;
-                            if (t < mc[c]) {
-                                const int jb = jv[c];
-                                const float2 q = xt[c];
-                                // each pair once: from its lower index, or (batch
-                                // energy, Eq. 7) from the batch's end
-                                bool hf = jb > i * (int)sizeof(float2);
-                                if constexpr (SEQ) if (masked) hf = hf || sq.bat[jb / (int)sizeof(float2)] != cb;
-                                float l2;
-                                const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
-                                                              ecA[c], e1cA[c], gxA[c], gyA[c], l2, kE1);
-                                // FP64 energies only where FP32 sees (nearly) an overlap:
-                                // outside a 1e-5 band the FP64 terms are zero
-                                if (kW64 && hf && l2 < four_r2_band)
-                                    pair_term64s(q, pj[c], l2 * il, il, two_r64, four_r2_64, eocA[c], etcA[c]);
+                            const int jb = jv[c];
+                            const float2 q = xt[c];
+                            // each pair once: from its lower index, or (batch
+                            // energy, Eq. 7) from the batch's end
+                            bool hf = jb > i * (int)sizeof(float2);
+                            if constexpr (SEQ) {
+                                const int jj = jb / (int)sizeof(float2);
+                                if (masked) hf = hf || sq.bat[jj < kMaxN ? jj : kMaxN - 1] != cb;
                             }
+                            float l2;
+                            const float il = pair_term32s(q, pj[c], hf, two_r, four_r2, four_r2_band,
+                                                          ecA[c], e1cA[c], gxA[c], gyA[c], l2, kE1);
+                            // FP64 energies only where FP32 sees (nearly) an overlap:
+                            // outside a 1e-5 band the FP64 terms are zero
+                            if (kW64 && hf && l2 < four_r2_band)
+                                pair_term64s(q, pj[c], l2 * il, il, two_r64, four_r2_64, eocA[c], etcA[c]);
                         }
                     }
                 };
@@ -1179,19 +1204,26 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     const int mm = __builtin_amdgcn_readfirstlane(sh.dk.m);
                     const int max_halvings = __builtin_amdgcn_readfirstlane(sh.dk.max_halvings);
                     const int max_iter = __builtin_amdgcn_readfirstlane(sh.dk.max_iter);
+                    // source slots of this lane's Gram update (read early)
+                    const uint32_t pa = sh.bperm[lane];
                     float tot = 0.f;
 #pragma unroll
                     for (int w = 0; w < kDW; ++w) tot += sh.red[par][w][lane];
                     double so = 0.0, st = 0.0;
                     if (want64) {
-                        // lane w holds wave w's FP64 sums; added in wave order
-                        const int wl = lane < kDW ? lane : 0;
-                        const double vo = sh.red64[par][wl][0], vt = sh.red64[par][wl][1];
-#pragma unroll
-                        for (int w = 0; w < kDW; ++w) {
-                            so += lane_value64(vo, w);
-                            st += lane_value64(vt, w);
-                        }
+                        // lane w of every group of eight holds wave w's FP64
+                        // sums; a fixed tree over the eight (pairs, quads,
+                        // halves), read from lane 0
+                        const int wl = lane & (kDW - 1);
+                        double vo = sh.red64[par][wl][0], vt = sh.red64[par][wl][1];
+                        vo += dpp64<kDppXor1>(vo);
+                        vt += dpp64<kDppXor1>(vt);
+                        vo += dpp64<kDppXor2>(vo);
+                        vt += dpp64<kDppXor2>(vt);
+                        vo += dpp64<kDppHalfMirror>(vo);
+                        vt += dpp64<kDppHalfMirror>(vt);
+                        so = lane_value64(vo, 0);
+                        st = lane_value64(vt, 0);
                     }
                     const float Et = lane_value(tot, sE);
                     const float E1t = lane_value(tot, sE1);
@@ -1217,8 +1249,45 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     if (accept) {
                         fl = kDecAccept | (push ? kDecPush : 0);
-                        gram_update_ring(tot, push, lane);
-                        if (push) k = k + 1 > mm ? mm : k + 1;
+                        // ---- Gram update, written into the ring before its
+                        // rows are read below (LDS keeps a wave's order).
+                        // Lane l (pair order of the updated basis) takes its
+                        // entries <g, b_l> and, on a push, <s, b_l> and
+                        // <y, b_l> of the new pair from the slot totals.
+                        const int hd_old = hd;
+                        if (push) {
+                            hd = hd == kMM - 1 ? 0 : hd + 1;
+                            k = k + 1 > mm ? mm : k + 1;
+                        }
+                        const int ti = __builtin_bit_cast(int, tot);
+                        const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                             (int)__builtin_amdgcn_ubfe(pa, push ? 8u : 0u, 8u), ti));
+                        const int sto = ring_at(lane < kNB ? lane : kG);      // storage slot of b_l
+                        const int c0 = sto < kMM ? sto : sto < kG ? sto + kMM : 4 * kMM;
+                        const int c1c = sto < kG ? c0 + kMM : 4 * kMM;        // its two columns
+                        float *rowl = &sh.Bring[sto * kRS];
+                        if (lane < kNB) {
+                            sh.Bring[kG * kRS + c0] = vg;
+                            sh.Bring[kG * kRS + c1c] = vg;
+                            rowl[4 * kMM] = vg;
+                        }
+                        if (push) {
+                            const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                 (int)__builtin_amdgcn_ubfe(pa, 16u, 8u), ti));
+                            const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                 (int)__builtin_amdgcn_ubfe(pa, 24u, 8u), ti));
+                            if (lane < kNB) {
+                                sh.Bring[hd_old * kRS + c0] = vs;
+                                sh.Bring[hd_old * kRS + c1c] = vs;
+                                sh.Bring[(kMM + hd_old) * kRS + c0] = vy;
+                                sh.Bring[(kMM + hd_old) * kRS + c1c] = vy;
+                                rowl[hd_old] = vs;
+                                rowl[kMM + hd_old] = vs;
+                                rowl[2 * kMM + hd_old] = vy;
+                                rowl[3 * kMM + hd_old] = vy;
+                            }
+                            if (lane == 0) sh.rho[0][hd_old] = 1.f / lane_value(tot, sScYc);
+                        }
                         if (req == kReqTrial) {
                             ++it;
                             itw = itw == W ? 0 : itw + 1;
@@ -1239,7 +1308,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         // square root is at most g_tol).  The tests are
                         // selects and the two-loop runs before their outcome
                         // is looked at, so both chains share the issue slots.
-                        const float gg = accept ? lane_value(tot, sGG) : sh.Bm[0][kG * kNB + kG];
+                        const float gg = accept ? lane_value(tot, sGG) : sh.Bring[kG * kRS + 4 * kMM];
                         const float gg0 = fmaxf(gg, 0.f);
                         const double Eacc = fp64 ? E64o : (double)E;
                         const int itn = itw == W ? 0 : itw + 1;       // (it + 1) mod (W + 1)
@@ -1250,8 +1319,23 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                : dtl                               ? 3
                                : it >= max_iter                    ? 5 : 0;
                         if (lane == itw) ehist = Eacc;                // read above before written
+                        // this lane's row of the updated B in pair order:
+                        // contiguous from offset hd in the ring row
+                        float Bc[kNB];
+                        {
+                            const float *row = &sh.Bring[ring_at(lane < kNB ? lane : kG) * kRS + hd];
+#pragma unroll
+                            for (int j = 0; j < kMM; ++j) {
+                                Bc[j] = row[j];
+                                Bc[kMM + j] = row[2 * kMM + j];
+                            }
+                            Bc[kG] = row[4 * kMM - hd];
+                        }
+                        const int jp = lane < kMM ? lane : lane - kMM;
+                        const bool live = lane < 2 * kMM && jp >= kMM - k;
+                        const float rho_l = sh.rho[0][ring_at(lane < 2 * kMM ? jp : 0)];
                         float cs_v, alph_v, gam;
-                        const float gpv = two_loop(lane, hd, cs_v, alph_v, gam);
+                        const float gpv = two_loop_core(lane, Bc, live ? rho_l : 0.f, cs_v, alph_v, gam);
                         if (status != 0) {
                             fl |= kDecStop;
                         } else {
@@ -1591,7 +1675,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // with the radius as a variable, E reports the energy without
             // the penalty (the last lambda was halved once more after the round)
             r.E32 = (ADJ && A.rounds > 0) ? E - 2.f * lam * Rz * Rz : E;
-            r.gnorm = sqrtf(fmaxf(sh.Bm[cur][kG * kNB + kG], 0.f));
+            r.gnorm = sqrtf(fmaxf(SOLO ? sh.Bring[kG * kRS + 4 * kMM] : sh.Bm[cur][kG * kNB + kG], 0.f));
             r.E64 = fp64 ? E64t : -1.0;
             if (SEQ && visits) {
                 // outer iterations; whole-instance energies; the sum of the

@@ -138,6 +138,24 @@ __device__ __forceinline__ float wave_sum_dpp(float v)
     return lane_value(v, 63);
 }
 
+// Maximum of a non-negative int over the 64 lanes, returned wave-uniform
+// (lanes a DPP pattern leaves out read 0, which no value is below).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dppi(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ int wave_max_dpp(int v)
+{
+    v = max(v, dppi<kDppXor1>(v));
+    v = max(v, dppi<kDppXor2>(v));
+    v = max(v, dppi<kDppHalfMirror>(v));
+    v = max(v, dppi<kDppRowMirror>(v));
+    v = max(v, dppi<kDppBcast15, 0xa>(v));
+    v = max(v, dppi<kDppBcast31, 0xc>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // The same sum for a double: each DPP step moves the two 32-bit halves.
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp64(double v)
@@ -286,6 +304,33 @@ __device__ __forceinline__ uint16_t gram_source(int ent, bool push)
     else if (kl == 0) sl = slot_new_old(ka, ol);
     else sl = slot_new_new(ka, kl);
     return (uint16_t)(0x8000 + sl);
+}
+
+// Whole-instance descent with B as a ring: the slots that lane l (basis
+// vector l in pair order of the UPDATED basis: s_0..s_9, y_0..y_9, g)
+// takes its new Gram entries from, as byte addresses for ds_bpermute
+// packed in one word: bits 0-7 <g, b_l> without a push, 8-15 <g, b_l>
+// with a push, 16-23 <s, b_l> and 24-31 <y, b_l> of the pushed pair.  A
+// push renumbers old pair j + 1 as pair j; the new pair is pair 9.
+__device__ __forceinline__ uint32_t gram_perm_bytes(int l)
+{
+    const bool is_g = l >= kG, is_s = l < kMM;
+    const int j = is_s ? l : (is_g ? 0 : l - kMM);
+    auto slot = [&](int kind, bool push) -> int {   // kind 3: g, 1: s, 2: y
+        const bool newp = push && j == kMM - 1;
+        const int jo = push ? j + 1 : j;
+        if (is_g) return kind == 3 ? sGG : kind == 1 ? sScG : sYcG;
+        if (newp) {
+            if (kind == 3) return is_s ? sScG : sYcG;
+            if (kind == 1) return is_s ? sScSc : sScYc;
+            return is_s ? sScYc : sYcYc;
+        }
+        if (kind == 3) return is_s ? sGS(jo) : sGY(jo);
+        if (kind == 1) return is_s ? sSS(jo) : sSY(jo);
+        return is_s ? sYS(jo) : sYY(jo);
+    };
+    return (uint32_t)(4 * slot(3, false)) | ((uint32_t)(4 * slot(3, true)) << 8) |
+           ((uint32_t)(4 * slot(1, true)) << 16) | ((uint32_t)(4 * slot(2, true)) << 24);
 }
 
 // FP64 neighbor predicate with an FP32 pre-test.  FP32 evaluation of
