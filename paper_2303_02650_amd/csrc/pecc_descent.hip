@@ -73,8 +73,10 @@ struct DescentShared {
     int over;                      // a circle had more than ELL neighbors
     int work;
     int cell_evals;                // evaluations over the cell grid (instance)
+    int npair[kMaxSeqBatches + 1]; // listed pairs i<j of the current lists: per batch, and in all
     // whole-instance descent: what the deciding wave leaves for the others
     int dec_flags;                 // kDec* bits
+    int dec_cb;                    // batch descent: the batch of the next evaluation
     int dec_req;                   // what the next evaluation is for
     int dec_fp64;                  // FP64 regime from the next evaluation on
     float dec_alpha;               // step length of the next trial
@@ -84,8 +86,8 @@ struct DescentShared {
     // they would crowd out the loop's scalar state)
     struct {
         double tau64, e_feasible;
-        float c1, eps_curv, ftol, g_tol_sq;
-        int m, max_halvings, max_iter, pad;
+        float c1, eps_curv, ftol, g_tol_sq, g_tol;
+        int m, max_halvings, max_iter, nbat, anm;
     } dk;
 };
 
@@ -271,7 +273,7 @@ struct NoShared {
 // Evaluation requests of the descent's state machine.
 enum : int { kReqInit = 0, kReqFp64 = 1, kReqTrial = 2, kReqTotal = 3 };
 // outcome of an evaluation in the whole-instance descent
-enum : int { kDecAccept = 1, kDecPush = 2, kDecStop = 4, kDecNext = 8, kDecSteepest = 16 };
+enum : int { kDecAccept = 1, kDecPush = 2, kDecStop = 4, kDecNext = 8, kDecSteepest = 16, kDecAnm = 32 };
 
 // ADJ: container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins
 // the variables, the objective is U = E + lambda R^2 and A.rounds
@@ -314,12 +316,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     constexpr bool DENSE = MODE == kModeDense;
     constexpr bool SEQ = MODE == kModeSeq || DENSE;
     // whole instance: one wave takes the uniform decisions of an evaluation
-    constexpr bool SOLO = MODE == kModeWhole;
+    constexpr bool SOLO = MODE == kModeWhole || MODE == kModeSeq;
     constexpr int ELL = SEQ ? kEllSeq : kEll;
     __shared__ DescentShared<ELL> sh;
     __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
+    // (lane ids are recomputed per evaluation from an opaque copy of tid)
     // wave index, wave-uniform to the compiler (branches on it stay scalar)
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int q = tid; q < 2 * kNB * kNB; q += kDB)
@@ -335,16 +337,16 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         __syncthreads();
         const int slot = sh.work;
         if (slot >= B) break;
+        // an opaque copy of the thread id for this instance: set-up addresses
+        // are recomputed per instance instead of staying live across them
+        int tid_i = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid_i));
+        const int tid = tid_i;
         const int b = queue[1 + slot];
         const int off = offset[b], n = offset[b + 1] - off;
         if (!(off >= 0 && n >= 0 && n <= kMaxN && (int64_t)off + n <= total_n)) {
             if (tid == 0) {
-                DescentHead r = {};
-                r.status = 7;  // BAD_INSTANCE
-                r.E32 = __builtin_nanf("");
-                r.gnorm = __builtin_nanf("");
-                r.E64 = -1.0;
-                store_result(out, b, r, 0);
+                store_bad_instance(out, b);   // BAD_INSTANCE
             }
             continue;
         }
@@ -389,12 +391,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             if (__syncthreads_or(bad)) {
                 if (tid == 0) {
-                    DescentHead r = {};
-                    r.status = 7;  // BAD_INSTANCE: a batch id out of range
-                    r.E32 = __builtin_nanf("");
-                    r.gnorm = __builtin_nanf("");
-                    r.E64 = -1.0;
-                    store_result(out, b, r, 0);
+                    store_bad_instance(out, b);   // BAD_INSTANCE: a batch id out of range
                 }
                 continue;
             }
@@ -440,12 +437,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             __syncthreads();
             if ((int64_t)sq.voff[A.nbat] > A.hstride) {
                 if (tid == 0) {
-                    DescentHead r = {};
-                    r.status = 7;  // BAD_INSTANCE: the matrices do not fit the workspace
-                    r.E32 = __builtin_nanf("");
-                    r.gnorm = __builtin_nanf("");
-                    r.E64 = -1.0;
-                    store_result(out, b, r, 0);
+                    store_bad_instance(out, b);   // BAD_INSTANCE: the matrices do not fit the workspace
                 }
                 continue;
             }
@@ -471,8 +463,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         int cur = 0;                   // Bm buffer in use
         int tcount = 0;                // evaluations so far (flag parity)
         bool overflow = false;         // list did not fit: sweep the cell grid
-        int half_mine[kCPT] = {};      // listed pairs i<j of this thread's circles
-        int64_t pair_mine = 0;         // summed over evaluations
+        int64_t pair_mine = 0;         // listed pairs i<j swept, summed over evaluations (uniform)
         int rebuilds = 0, evals = 0;
         bool fp64 = false;
         double E64o = 0.0, E64t = -1.0;   // FP64 energies (objective / unit circles)
@@ -524,9 +515,12 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // (same predicate; as sets).  Different (or the stored lists did not
         // fit): the next evaluation rebuilds them and len = 1; equal: len
         // doubles.  Returns whether the lists change.
-        auto anm_step = [&]() -> bool {
+        auto anm_tick = [&]() -> bool {
             if (++anm_cnt < anm_len) return false;
             anm_cnt = 0;
+            return true;
+        };
+        auto anm_compare = [&]() -> bool {
             const int t0 = (int)threadIdx.x;
 #pragma unroll
             for (int c = 0; c < kCPT; ++c)
@@ -561,6 +555,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             }
             return changed;
         };
+        auto anm_step = [&]() -> bool { return anm_tick() && anm_compare(); };
         // dense batch descent (Eq. 8-11).  Each batch's matrix is kept one
         // update behind: the stored S, a known pending update K = (s_K, w_K,
         // 1/beta_K, a2_K) and the newest curvature pair Q = (s_Q, y_Q, beta_Q)
@@ -817,6 +812,46 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (q >= kMM) q -= kMM;
             return base + q;
         };
+        // the first of the two ring columns of storage slot c (g: its one column)
+        auto ring_col = [](int c) -> int { return c < kMM ? c : c < kG ? c + kMM : 4 * kMM; };
+        // batch descent, deciding wave: batch bb's saved Gram matrix (pair
+        // order) into the ring, pair 0 at storage 0; and back.  ln: the lane
+        // (from the loop's opaque thread id, so that no index stays live
+        // across the loop)
+        auto ring_load = [&](int bb, int ln) {
+            if constexpr (SEQ && !DENSE) {
+                hd = 0;
+                constexpr int kQ = (kNB * kNB + kWave - 1) / kWave;
+                float v[kQ];
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int e = ln + kWave * q;
+                    v[q] = e < kNB * kNB ? sq.BmP[bb][e] : 0.f;
+                }
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int e = ln + kWave * q;
+                    if (e < kNB * kNB) {
+                        const int r = e / kNB, c = e - r * kNB;       // storage = pair order
+                        float *dst = &sh.Bring[r * kRS + ring_col(c)];
+                        dst[0] = v[q];
+                        if (c < kG) dst[kMM] = v[q];                   // the second copy
+                    }
+                }
+            }
+        };
+        auto ring_save = [&](int bb, int ln) {
+            if constexpr (SEQ && !DENSE) {
+#pragma unroll
+                for (int q = 0; q < (kNB * kNB + kWave - 1) / kWave; ++q) {
+                    const int e = ln + kWave * q;
+                    if (e < kNB * kNB) {
+                        const int a = e / kNB, b2 = e - a * kNB;
+                        sq.BmP[bb][e] = sh.Bring[ring_at(a) * kRS + ring_col(ring_at(b2))];
+                    }
+                }
+            }
+        };
         // Two-loop recursion on B. Lane l holds row l of B (the basis
         // s_0..s_9, y_0..y_9, g), so acc = (B c) for the current coefficient
         // vector c is one FMA per lane per step: q = g - sum_i a_i y_i gives
@@ -897,7 +932,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             sh.pos[kMaxN] = make_float2(kFarCoord, kFarCoord);
             sh.dk.tau64 = A.tau64; sh.dk.e_feasible = A.e_feasible;
             sh.dk.c1 = A.c1; sh.dk.eps_curv = A.eps_curv; sh.dk.ftol = A.ftol; sh.dk.g_tol_sq = A.g_tol_sq;
-            sh.dk.m = A.m; sh.dk.max_halvings = A.max_halvings; sh.dk.max_iter = A.max_iter; sh.dk.pad = 0;
+            sh.dk.m = A.m; sh.dk.max_halvings = A.max_halvings; sh.dk.max_iter = A.max_iter;
+            sh.dk.g_tol = A.g_tol; sh.dk.nbat = A.nbat; sh.dk.anm = A.anm;
         }
 
         // container adjustment state (uniform): radius, its gradient and
@@ -959,6 +995,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (sh.flag[par]) {
                 // ---- neighbor list rebuild at the positions in sh.pos -------
                 if (tid == 0) sh.over = 0;    // set again below only after bin_circles' barriers
+                if (tid <= kMaxSeqBatches) sh.npair[tid] = 0;
                 bin_circles<kDB>(sh.pos, n, grid, sh.cell_start, sh.cell_circ, sh.slot_tmp,
                                  sh.scan_tmp);
                 // ascending circle index inside every cell: lists (cells in
@@ -977,6 +1014,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 // one pass: every circle writes its neighbors into its own
                 // ELL slots; more than ELL switches this list epoch to
                 // sweeping the cell grid instead
+                int up_c[kCPT] = {};
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = tid + c * kDB;
@@ -999,8 +1037,24 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         }
                         if (m > ELL) sh.over = 1;
                         sh.list_n[i] = (uint8_t)(m < ELL ? m : ELL);
-                        half_mine[c] = up;
+                        up_c[c] = up;
                         xr[c] = xt[c];
+                    }
+                }
+                // listed pairs from their lower index, per wave, then one
+                // integer add per wave (the same totals in any order): in all,
+                // and per batch for the batch descent
+                {
+                    const int wsum = wave_sum_int(up_c[0] + up_c[1]);
+                    if (lane == 0) atomicAdd(&sh.npair[kMaxSeqBatches], wsum);
+                    if constexpr (SEQ) {
+                        for (int q = 0; q < A.nbat; ++q) {
+                            int v = 0;
+#pragma unroll
+                            for (int c = 0; c < kCPT; ++c) v += (act[c] && batc_of(c) == q) ? up_c[c] : 0;
+                            v = wave_sum_int(v);
+                            if (lane == 0 && v != 0) atomicAdd(&sh.npair[q], v);
+                        }
                     }
                 }
                 // pad every list with the far point up to the longest list
@@ -1027,8 +1081,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // evaluations over the cell grid, counted in LDS (no register
             // stays live for a number read once at the end)
             if (overflow && tid == 0) ++sh.cell_evals;
-#pragma unroll
-            for (int c = 0; c < kCPT; ++c) pair_mine += inb[c] ? half_mine[c] : 0;
+            pair_mine += __builtin_amdgcn_readfirstlane(sh.npair[masked ? cb : kMaxSeqBatches]);
             // ---- pair sweep: energy and gradient of this thread's circles ----
             // Both circles of the thread walk their lists in one loop, so their
             // list and position reads overlap; each circle still adds its
@@ -1071,10 +1124,14 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         const int tn = t + 1 < ELL ? t + 1 : ELL - 1;
 #pragma unroll
                         for (int c = 0; c < kCPT; ++c) {
-                            jv[c] = jn[c];
-                            // batch visit: circles outside the batch take the far point
-                            if constexpr (SEQ) if (masked) jv[c] = use[c] ? jv[c] : kFarOff;
-                            jn[c] = sh.list[tn][tid + c * kDB];
+                            if constexpr (SEQ) {
+                                // batch visit: circles outside the batch take the far point
+                                jv[c] = sh.list[t][tid + c * kDB];
+                                if (masked) jv[c] = use[c] ? jv[c] : kFarOff;
+                            } else {
+                                jv[c] = jn[c];
+                                jn[c] = sh.list[tn][tid + c * kDB];
+                            }
                         }
 #pragma unroll
                         for (int c = 0; c < kCPT; ++c)
@@ -1227,133 +1284,220 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     }
                     const float Et = lane_value(tot, sE);
                     const float E1t = lane_value(tot, sE1);
+                    // batch descent: more than one batch, visited in turn
+                    const bool vis = SEQ && visits;
                     int fl = 0;
                     bool accept = false, push = false;
-                    if (req == kReqTrial) {
-                        const bool ok = fp64 ? so <= E64o + (double)c1 * (double)alpha * (double)gp
-                                             : Et <= E + c1 * alpha * gp;
-                        if (ok) {
-                            accept = true;
-                            const float sy = lane_value(tot, sScYc), yy = lane_value(tot, sYcYc);
-                            push = sy > eps_curv * yy;
-                        } else {
-                            alpha *= 0.5f;
-                            if (++h > max_halvings) { status = 4; fl = kDecStop; }   // STALLED
-                            else fl = kDecNext;
-                        }
-                    } else if (req == kReqInit) {
-                        accept = true;   // g and the g row of B from this evaluation
-                    } else {             // kReqFp64: FP64 energies of the current point
+                    bool vend = false;         // batch descent: the visit ends with this evaluation
+                    if (vis && req == kReqTotal) {
+                        // ---- top of an outer iteration: stop tests on the
+                        // whole instance (FP64 energies of every circle), then
+                        // the first batch's visit
+                        E_tot = Et;
                         E64o = so;
                         E64t = st;
-                    }
-                    if (accept) {
-                        fl = kDecAccept | (push ? kDecPush : 0);
-                        // ---- Gram update, written into the ring before its
-                        // rows are read below (LDS keeps a wave's order).
-                        // Lane l (pair order of the updated basis) takes its
-                        // entries <g, b_l> and, on a push, <s, b_l> and
-                        // <y, b_l> of the new pair from the slot totals.
-                        const int hd_old = hd;
-                        if (push) {
-                            hd = hd == kMM - 1 ? 0 : hd + 1;
-                            k = k + 1 > mm ? mm : k + 1;
-                        }
-                        const int ti = __builtin_bit_cast(int, tot);
-                        const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
-                                             (int)__builtin_amdgcn_ubfe(pa, push ? 8u : 0u, 8u), ti));
-                        const int sto = ring_at(lane < kNB ? lane : kG);      // storage slot of b_l
-                        const int c0 = sto < kMM ? sto : sto < kG ? sto + kMM : 4 * kMM;
-                        const int c1c = sto < kG ? c0 + kMM : 4 * kMM;        // its two columns
-                        float *rowl = &sh.Bring[sto * kRS];
-                        if (lane < kNB) {
-                            sh.Bring[kG * kRS + c0] = vg;
-                            sh.Bring[kG * kRS + c1c] = vg;
-                            rowl[4 * kMM] = vg;
-                        }
-                        if (push) {
-                            const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
-                                                 (int)__builtin_amdgcn_ubfe(pa, 16u, 8u), ti));
-                            const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
-                                                 (int)__builtin_amdgcn_ubfe(pa, 24u, 8u), ti));
-                            if (lane < kNB) {
-                                sh.Bring[hd_old * kRS + c0] = vs;
-                                sh.Bring[hd_old * kRS + c1c] = vs;
-                                sh.Bring[(kMM + hd_old) * kRS + c0] = vy;
-                                sh.Bring[(kMM + hd_old) * kRS + c1c] = vy;
-                                rowl[hd_old] = vs;
-                                rowl[kMM + hd_old] = vs;
-                                rowl[2 * kMM + hd_old] = vy;
-                                rowl[3 * kMM + hd_old] = vy;
-                            }
-                            if (lane == 0) sh.rho[0][hd_old] = 1.f / lane_value(tot, sScYc);
-                        }
-                        if (req == kReqTrial) {
-                            ++it;
-                            itw = itw == W ? 0 : itw + 1;
-                        }
-                        E = Et;
-                        if (fp64) { E64o = so; E64t = st; }
-                        // FP64 regime once either FP32 energy is small
-                        if (!fp64 && tau64 > 0.0 && (double)fminf(E, E1t) < tau64) {
-                            fp64 = true;
-                            req = kReqFp64;          // FP64 energies of x before going on
-                            fl |= kDecNext;
-                        }
-                    }
-                    if (!(fl & (kDecNext | kDecStop))) {
-                        // ---- top of an iteration: stop tests, direction
-                        // |g| <= g_tol and |g| finite, decided on |g|^2 (no
-                        // square root: g_tol_sq is the largest value whose
-                        // square root is at most g_tol).  The tests are
-                        // selects and the two-loop runs before their outcome
-                        // is looked at, so both chains share the issue slots.
-                        const float gg = accept ? lane_value(tot, sGG) : sh.Bring[kG * kRS + 4 * kMM];
-                        const float gg0 = fmaxf(gg, 0.f);
-                        const double Eacc = fp64 ? E64o : (double)E;
-                        const int itn = itw == W ? 0 : itw + 1;       // (it + 1) mod (W + 1)
-                        const bool dtl = ftol > 0.f && it >= W && decreased_too_little(Eacc, itn, ftol);
-                        status = (!isfinite(E) || !isfinite(gg0)) ? 6
-                               : (fp64 && E64t < e_feasible)      ? 1
-                               : gg0 <= g_tol_sq                   ? 2
-                               : dtl                               ? 3
-                               : it >= max_iter                    ? 5 : 0;
-                        if (lane == itw) ehist = Eacc;                // read above before written
-                        // this lane's row of the updated B in pair order:
-                        // contiguous from offset hd in the ring row
-                        float Bc[kNB];
-                        {
-                            const float *row = &sh.Bring[ring_at(lane < kNB ? lane : kG) * kRS + hd];
-#pragma unroll
-                            for (int j = 0; j < kMM; ++j) {
-                                Bc[j] = row[j];
-                                Bc[kMM + j] = row[2 * kMM + j];
-                            }
-                            Bc[kG] = row[4 * kMM - hd];
-                        }
-                        const int jp = lane < kMM ? lane : lane - kMM;
-                        const bool live = lane < 2 * kMM && jp >= kMM - k;
-                        const float rho_l = sh.rho[0][ring_at(lane < 2 * kMM ? jp : 0)];
-                        float cs_v, alph_v, gam;
-                        const float gpv = two_loop_core(lane, Bc, live ? rho_l : 0.f, cs_v, alph_v, gam);
+                        const double Eacc = fp64 ? E64o : (double)E_tot;
+                        const bool dtl = ftol > 0.f && it >= W && decreased_too_little(Eacc, (it - W) % (W + 1), ftol);
+                        status = !isfinite(E_tot)                          ? 6
+                               : E64t < e_feasible                         ? 1
+                               : (it > 0 && gsum_prev <= ufl(sh.dk.g_tol))  ? 2
+                               : dtl                                        ? 3
+                               : (it > 0 && nvis > 0 && nstall == nvis)     ? 4
+                               : it >= max_iter                             ? 5 : 0;
+                        if (lane == it % (W + 1)) ehist = Eacc;
                         if (status != 0) {
-                            fl |= kDecStop;
+                            fl = kDecStop;
                         } else {
-                            gp = gpv;
-                            if (k > 0 && !(gp < 0.f)) {
-                                k = 0;
-                                gp = -gg;
-                                fl |= kDecSteepest;
+                            if (!fp64 && tau64 > 0.0 && (double)fminf(E_tot, E1t) < tau64) fp64 = true;
+                            gsum = 0.f;
+                            nvis = 0;
+                            nstall = 0;
+                            cb = first_b;
+                            ring_load(cb, lane);
+                            k = __builtin_amdgcn_readlane(kb_v, cb);
+                            req = kReqInit;
+                            fl = kDecNext;
+                        }
+                    } else {
+                        if (req == kReqTrial) {
+                            const bool ok = fp64 ? so <= E64o + (double)c1 * (double)alpha * (double)gp
+                                                 : Et <= E + c1 * alpha * gp;
+                            if (ok) {
+                                accept = true;
+                                const float sy = lane_value(tot, sScYc), yy = lane_value(tot, sYcYc);
+                                push = sy > eps_curv * yy;
+                                vend = vis;
+                            } else {
+                                alpha *= 0.5f;
+                                if (++h > max_halvings) {
+                                    if (!vis) { status = 4; fl = kDecStop; }   // STALLED
+                                    else { vend = true; ++nstall; }           // the batch stays
+                                } else {
+                                    fl = kDecNext;
+                                }
                             }
-                            if (k > 0) alpha = 1.f;
-                            else alpha = 1.f / fmaxf(1.f, sqrtf(gg0));
-                            h = 0;
-                            req = kReqTrial;
-                            if (lane < kMM) {
-                                sh.coef[0][lane] = cs_v;
-                                sh.coef[1][lane] = -gam * alph_v;
+                        } else if (req == kReqInit) {
+                            accept = true;   // g and the g row of B from this evaluation
+                        } else {             // kReqFp64: FP64 energies of the current point
+                            E64o = so;
+                            E64t = st;
+                        }
+                        if (accept) {
+                            fl = kDecAccept | (push ? kDecPush : 0);
+                            // ---- Gram update, written into the ring before its
+                            // rows are read below (LDS keeps a wave's order).
+                            // Lane l (pair order of the updated basis) takes its
+                            // entries <g, b_l> and, on a push, <s, b_l> and
+                            // <y, b_l> of the new pair from the slot totals.
+                            const int hd_old = hd;
+                            if (push) {
+                                hd = hd == kMM - 1 ? 0 : hd + 1;
+                                k = k + 1 > mm ? mm : k + 1;
                             }
-                            if (lane == 0) sh.dec_gam = gam;
+                            const int ti = __builtin_bit_cast(int, tot);
+                            const float vg = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                 (int)__builtin_amdgcn_ubfe(pa, push ? 8u : 0u, 8u), ti));
+                            const int sto = ring_at(lane < kNB ? lane : kG);      // storage slot of b_l
+                            const int c0 = ring_col(sto);
+                            const int c1c = sto < kG ? c0 + kMM : c0;             // its two columns
+                            float *rowl = &sh.Bring[sto * kRS];
+                            if (lane < kNB) {
+                                sh.Bring[kG * kRS + c0] = vg;
+                                sh.Bring[kG * kRS + c1c] = vg;
+                                rowl[4 * kMM] = vg;
+                            }
+                            if (push) {
+                                const float vs = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                     (int)__builtin_amdgcn_ubfe(pa, 16u, 8u), ti));
+                                const float vy = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                                                     (int)__builtin_amdgcn_ubfe(pa, 24u, 8u), ti));
+                                if (lane < kNB) {
+                                    sh.Bring[hd_old * kRS + c0] = vs;
+                                    sh.Bring[hd_old * kRS + c1c] = vs;
+                                    sh.Bring[(kMM + hd_old) * kRS + c0] = vy;
+                                    sh.Bring[(kMM + hd_old) * kRS + c1c] = vy;
+                                    rowl[hd_old] = vs;
+                                    rowl[kMM + hd_old] = vs;
+                                    rowl[2 * kMM + hd_old] = vy;
+                                    rowl[3 * kMM + hd_old] = vy;
+                                }
+                                if (!SEQ && lane == 0) sh.rho[0][hd_old] = 1.f / lane_value(tot, sScYc);
+                            }
+                            if (req == kReqTrial && !vis) {
+                                ++it;
+                                itw = itw == W ? 0 : itw + 1;
+                            }
+                            E = Et;
+                            if (fp64) { E64o = so; E64t = st; }
+                            // FP64 regime once either FP32 energy is small
+                            if (!vis && !fp64 && tau64 > 0.0 && (double)fminf(E, E1t) < tau64) {
+                                fp64 = true;
+                                req = kReqFp64;          // FP64 energies of x before going on
+                                fl |= kDecNext;
+                            }
+                        }
+                        if constexpr (SEQ) {
+                            const int nbat = __builtin_amdgcn_readfirstlane(sh.dk.nbat);
+                            const bool anm = __builtin_amdgcn_readfirstlane(sh.dk.anm) != 0;
+                            if (vend) {
+                                // ---- end of a visit: the batch's Gram matrix and
+                                // history count are saved, then the next batch
+                                kb_v = lane == cb ? k : kb_v;
+                                ring_save(cb, lane);
+                                int nx = cb + 1;
+                                while (nx < nbat && sq.cnt[nx] == 0) ++nx;
+                                if (nx >= nbat) {           // outer iteration done
+                                    ++it;
+                                    gsum_prev = gsum;
+                                    // ANM (Alg. 3) by every wave after the barrier
+                                    if (anm && anm_tick()) fl |= kDecAnm;
+                                    req = kReqTotal;
+                                } else {
+                                    cb = nx;
+                                    ring_load(cb, lane);
+                                    k = __builtin_amdgcn_readlane(kb_v, cb);
+                                    req = kReqInit;
+                                }
+                                fl |= kDecNext;
+                            } else if (!vis && anm && it > anm_it && !(fl & (kDecNext | kDecStop))) {
+                                // one batch: ANM after every iteration; the point
+                                // is evaluated again over the lists it leaves
+                                anm_it = it;
+                                if (anm_tick()) {
+                                    fl |= kDecAnm | kDecNext;
+                                    req = kReqInit;
+                                }
+                            }
+                        }
+                        if (!(fl & (kDecNext | kDecStop))) {
+                            // ---- top of an iteration: stop tests, direction
+                            // |g| <= g_tol and |g| finite, decided on |g|^2 (no
+                            // square root: g_tol_sq is the largest value whose
+                            // square root is at most g_tol).  The tests are
+                            // selects and the two-loop runs before their outcome
+                            // is looked at, so both chains share the issue slots.
+                            // A batch visit has no stop test of its own: its
+                            // gradient norm joins the outer iteration's sum.
+                            const float gg = accept ? lane_value(tot, sGG) : sh.Bring[kG * kRS + 4 * kMM];
+                            const float gg0 = fmaxf(gg, 0.f);
+                            if (vis) {
+                                gsum += sqrtf(gg0);
+                                ++nvis;
+                                status = 0;
+                            } else {
+                                const double Eacc = fp64 ? E64o : (double)E;
+                                const int itn = itw == W ? 0 : itw + 1;       // (it + 1) mod (W + 1)
+                                const bool dtl = ftol > 0.f && it >= W && decreased_too_little(Eacc, itn, ftol);
+                                status = (!isfinite(E) || !isfinite(gg0)) ? 6
+                                       : (fp64 && E64t < e_feasible)      ? 1
+                                       : gg0 <= g_tol_sq                   ? 2
+                                       : dtl                               ? 3
+                                       : it >= max_iter                    ? 5 : 0;
+                                if (lane == itw) ehist = Eacc;                // read above before written
+                            }
+                            // this lane's row of the updated B in pair order:
+                            // contiguous from offset hd in the ring row
+                            float Bc[kNB];
+                            const int jp = lane < kMM ? lane : lane - kMM;
+                            const bool live = lane < 2 * kMM && jp >= kMM - k;
+                            float rho_l;
+                            {
+                                const float *row = &sh.Bring[ring_at(lane < kNB ? lane : kG) * kRS + hd];
+#pragma unroll
+                                for (int j = 0; j < kMM; ++j) {
+                                    Bc[j] = row[j];
+                                    Bc[kMM + j] = row[2 * kMM + j];
+                                }
+                                Bc[kG] = row[4 * kMM - hd];
+                                if constexpr (SEQ) {
+                                    // 1 / s_j'y_j from the row (no store of it per batch):
+                                    // lane j reads <s_j, y_j>, lane 10 + j <y_j, s_j>
+                                    rho_l = 1.f / row[lane < kMM ? 2 * kMM + lane : (lane < 2 * kMM ? lane - kMM : 0)];
+                                } else {
+                                    rho_l = sh.rho[0][ring_at(lane < 2 * kMM ? jp : 0)];
+                                }
+                            }
+                            float cs_v, alph_v, gam;
+                            const float gpv = two_loop_core(lane, Bc, live ? rho_l : 0.f, cs_v, alph_v, gam);
+                            if (status != 0) {
+                                fl |= kDecStop;
+                            } else {
+                                gp = gpv;
+                                if (k > 0 && !(gp < 0.f)) {
+                                    k = 0;
+                                    gp = -gg;
+                                    fl |= kDecSteepest;
+                                }
+                                if (k > 0) alpha = 1.f;
+                                else alpha = 1.f / fmaxf(1.f, sqrtf(gg0));
+                                h = 0;
+                                req = kReqTrial;
+                                if (lane < kMM) {
+                                    sh.coef[0][lane] = cs_v;
+                                    sh.coef[1][lane] = -gam * alph_v;
+                                }
+                                if (lane == 0) sh.dec_gam = gam;
+                            }
                         }
                     }
                     if (lane == 0) {
@@ -1361,6 +1505,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         sh.dec_req = req;
                         sh.dec_fp64 = fp64 ? 1 : 0;
                         sh.dec_alpha = alpha;
+                        sh.dec_cb = cb;
                     }
                 }
                 __syncthreads();                                        // B3
@@ -1369,11 +1514,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 fp64 = __builtin_amdgcn_readfirstlane(sh.dec_fp64) != 0;
                 alpha = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                                       __builtin_bit_cast(int, sh.dec_alpha)));
+                if constexpr (SEQ) cb = __builtin_amdgcn_readfirstlane(sh.dec_cb);
                 if (fl & kDecAccept) {
                     const bool push = (fl & kDecPush) != 0;
 #pragma unroll
                     for (int c = 0; c < kCPT; ++c) {
-                        if (push) {
+                        // a batch visit's pair belongs to the batch's circles
+                        if (push && inb[c]) {
 #pragma unroll
                             for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
                             S[kMM - 1][c] = sc[c];
@@ -1383,12 +1530,17 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         g[c] = gt[c];
                     }
                 }
+                if constexpr (SEQ)
+                    if (fl & kDecAnm) anm_compare();                    // every wave
                 if (fl & kDecStop) break;
                 if (fl & kDecNext) continue;
-                // ---- direction p = -(gamma g + sum_j cs_j s_j + cy_j y_j)
+                // ---- direction p = -(gamma g + sum_j cs_j s_j + cy_j y_j),
+                // zero outside the visited batch
                 if (fl & kDecSteepest) {
 #pragma unroll
-                    for (int c = 0; c < kCPT; ++c) p[c] = make_float2(-g[c].x, -g[c].y);
+                    for (int c = 0; c < kCPT; ++c)
+                        p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(-g[c].x, -g[c].y)
+                                                                  : make_float2(0.f, 0.f);
                 } else {
                     const float gam = sh.dec_gam;
 #pragma unroll
@@ -1400,7 +1552,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             px -= csj * S[j][c].x + cyj * Y[j][c].x;
                             py -= csj * S[j][c].y + cyj * Y[j][c].y;
                         }
-                        p[c] = make_float2(px, py);
+                        p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(px, py)
+                                                                  : make_float2(0.f, 0.f);
                     }
                 }
                 continue;
@@ -1649,19 +1802,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         }   // rounds
 
         // ---- write back ------------------------------------------------------
-        {
-            // listed pairs i<j summed over evaluations (each pair once: by the
-            // thread of its lower index)
-            unsigned long long pm = (unsigned long long)pair_mine;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) pm += __shfl_xor(pm, o, kWave);
-            __syncthreads();
-            if (lane == 0) sh.red64[0][wv][0] = __builtin_bit_cast(double, pm);
-            __syncthreads();
-            pm = 0;
-            for (int w = 0; w < kDW; ++w) pm += __builtin_bit_cast(unsigned long long, sh.red64[0][w][0]);
-            pair_mine = (int64_t)pm;
-        }
 #pragma unroll
         for (int c = 0; c < kCPT; ++c)
             if (act[c]) reinterpret_cast<float2 *>(xy)[off + tid + c * kDB] = x[c];

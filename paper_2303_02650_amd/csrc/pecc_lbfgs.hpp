@@ -55,6 +55,23 @@ __device__ __forceinline__ void store_result(DescentResultDev *out, int b, const
     *reinterpret_cast<int2 *>(o + sizeof(DescentHead)) = make_int2(cell_evals, 0);
 }
 
+// The result of an instance that is not descended (status BAD_INSTANCE,
+// energies NaN, E64 = -1).  The constants pass through an empty asm so the
+// compiler materialises them here, on this rare path, instead of keeping
+// them in registers across the whole descent loop.
+__device__ __forceinline__ void store_bad_instance(DescentResultDev *out, int b)
+{
+    float qnan = __builtin_nanf("");
+    double m1 = -1.0;
+    asm volatile("" : "+v"(qnan), "+v"(m1));
+    DescentHead r = {};
+    r.status = 7;
+    r.E32 = qnan;
+    r.gnorm = qnan;
+    r.E64 = m1;
+    store_result(out, b, r, 0);
+}
+
 // Value of reduction slot v summed over this thread's circles (v is a
 // constant after unrolling, so the branches fold away): one FMA chain over
 // the circles' coordinates, started by a product.
@@ -153,6 +170,18 @@ __device__ __forceinline__ int wave_max_dpp(int v)
     v = max(v, dppi<kDppRowMirror>(v));
     v = max(v, dppi<kDppBcast15, 0xa>(v));
     v = max(v, dppi<kDppBcast31, 0xc>(v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Sum of an int over the 64 lanes (exact), returned wave-uniform.
+__device__ __forceinline__ int wave_sum_int(int v)
+{
+    v += dppi<kDppXor1>(v);
+    v += dppi<kDppXor2>(v);
+    v += dppi<kDppHalfMirror>(v);
+    v += dppi<kDppRowMirror>(v);
+    v += dppi<kDppBcast15, 0xa>(v);
+    v += dppi<kDppBcast31, 0xc>(v);
     return __builtin_amdgcn_readlane(v, 63);
 }
 
