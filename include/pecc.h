@@ -166,7 +166,7 @@ typedef struct pecc_descent_params {
     float   contact_margin; /* mu >= 0: the descent works on circles of radius 1+mu */
     double  e_feasible;     /* FEASIBLE when FP64 E of unit circles < this (1e-20) */
     double  tau64;          /* FP64 regime once min(E32, FP32 E of unit circles)
-                               < tau64 (1e-5): from then on every evaluation also
+                               < tau64 (3e-6): from then on every evaluation also
                                forms the FP64 energies, the sufficient-decrease
                                test uses them and FEASIBLE can be decided;
                                0 = never                                        */

@@ -253,7 +253,7 @@ class DescentParams:
     ftol: float = 1e-7
     contact_margin: float = 0.0
     e_feasible: float = 1e-20
-    tau64: float = 1e-5
+    tau64: float = 3e-6
 
     def c(self) -> pecc_descent_params:
         return pecc_descent_params(**asdict(self))

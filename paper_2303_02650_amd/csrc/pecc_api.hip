@@ -131,7 +131,7 @@ void pecc_descent_params_default(pecc_descent_params *p)
     p->ftol = 1e-7f;
     p->contact_margin = 0.f;
     p->e_feasible = 1e-20;
-    p->tau64 = 1e-5;
+    p->tau64 = 3e-6;
 }
 
 int pecc_lbfgs_descend_workspace_size(const pecc_instances *inst, size_t *bytes)

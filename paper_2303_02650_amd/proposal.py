@@ -40,9 +40,9 @@ E_FEASIBLE = 1e-20
 
 def ssed_params(max_iter: int = 5000) -> DescentParams:
     """Descent settings of the restarts: FP32 working-precision stop, contact
-    margin 1e-4, FP64 sufficient-decrease test below E = 1e-5."""
+    margin 1e-4, FP64 sufficient-decrease test below E = 3e-6."""
     return DescentParams(max_iter=max_iter, g_tol=1e-6, ftol=1e-7, ftol_window=20,
-                         contact_margin=1e-4, tau64=1e-5)
+                         contact_margin=1e-4, tau64=3e-6)
 
 
 def disk_points(rng: np.random.Generator, count: int, R: float) -> np.ndarray:

@@ -123,7 +123,7 @@ def test_default_params_match_header(P):
     d = P.default_params()
     assert d.m == 10 and d.max_iter == 5000 and d.max_halvings == 40
     assert abs(d.cutoff - 2.3) < 1e-6 and abs(d.skin_half - 0.15) < 1e-7
-    assert d.e_feasible == 1e-20 and d.tau64 == 1e-5
+    assert d.e_feasible == 1e-20 and d.tau64 == 3e-6
 
 
 def test_learned_proposal_entry_points_reject_bad_arguments(P):

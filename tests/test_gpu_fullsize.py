@@ -28,7 +28,7 @@ def test_main_step_full_size_sampled(P):
     d = P.DeviceInstances.from_host(inst.offset, inst.R)
     xy = torch.from_numpy(inst.xy.reshape(-1).copy()).cuda()
     prm = P.DescentParams(max_iter=5000, g_tol=1e-6, ftol=1e-7, ftol_window=20,
-                          contact_margin=1e-4, tau64=1e-5)
+                          contact_margin=1e-4, tau64=3e-6)
     res = P.results(P.lbfgs_descend(d, xy, prm))
     e64, mp, mc, feas = (t.cpu().numpy() for t in P.verify(d, xy))
     x = xy.cpu().numpy().reshape(-1, 2)
