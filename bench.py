@@ -152,7 +152,8 @@ def kbatch_study(P, a, dev, stream):
                 "kernel_ms": ms, "descents_per_s": dd.B / (ms / 1e3),
                 "matrix_bytes_per_instance": 4 * k * (2 * mb) ** 2,
                 "matrix_GBs_if_every_visit_updates": mbytes / (ms / 1e3) / 1e9,
-                "outer_iters_mean": float(r["iters"].mean()), "evals_mean": float(r["evals"].mean()),
+                "outer_iters_mean": float(r["iters"].mean()), "outer_iters_max": int(r["iters"].max()),
+                "evals_mean": float(r["evals"].mean()),
                 "E64_mean": float(e64d.cpu().numpy().mean()),
                 "feasible_fraction": float(feasd.cpu().numpy().mean()),
                 "status_counts": {P.STATUS[s]: int((r["status"] == s).sum()) for s in np.unique(r["status"])}}
@@ -166,6 +167,8 @@ def kbatch_study(P, a, dev, stream):
                 dense["best"] = {"best_k": kb, "best_ms": cand[kb], "ratio_to_k1": cand[kb] / t1}
         dense["workload"] = (f"{dd.B} random starts, n=1000, R=34.4 (seed 3); sector batches, one "
                              f"dense FP32 inverse-Hessian matrix per batch (Eq. 8-11)")
+        if a.dense_rate_iters > 0:
+            dense["matrix_pass_rate"] = dense_pass_rate(P, a, dev, stream)
     whole = descent_params(P, a.max_iter).c()
     x.copy_(x0)
     wws = torch.empty(P.pecc_lbfgs_descend_workspace_size(d), dtype=torch.uint8, device=dev)
@@ -179,6 +182,51 @@ def kbatch_study(P, a, dev, stream):
                         f"with skin 0.15, or ANM with l_cut 4",
             "settings": table, "best_k_by_partition": summary, "dense_bfgs": dense,
             "whole_instance_descent_ms": e0.elapsed_time(e1)}
+
+
+def dense_pass_rate(P, a, dev, stream):
+    """Matrix throughput of the dense k = 1 descent with every start busy for
+    the whole launch: g_tol = ftol = 0, so each start runs the same number of
+    outer iterations (a.dense_rate_iters, unless a line search stalls) and
+    each workgroup streams its 2000 x 2000 FP32 matrix for the whole
+    kernel.  Matrix bytes: the first two visits do not touch the matrix
+    (H = I, no update known yet), the third writes it without reading it,
+    every later one reads and writes it once; per start (2 t - 5) x 16 MB for
+    t outer iterations.  With B <= compute units one workgroup runs per CU,
+    so bytes / kernel time / B is the rate of one CU."""
+    import torch
+    import synth
+    out = {}
+    for B in (64, a.kbatch_dense_instances):
+        if B <= 0 or str(B) in out:
+            continue
+        c = synth.C4(B)
+        d = P.DeviceInstances.from_host(c.offset, c.R)
+        x = torch.from_numpy(c.xy.reshape(-1)).to(dev)
+        bo = torch.zeros(d.total_n, dtype=torch.int32, device=dev)
+        res_b = torch.empty(d.B * P.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        ws = torch.empty(P.pecc_gbo_kbatch_bfgs_workspace_size(d, 1000), dtype=torch.uint8, device=dev)
+        prm = descent_params(P, a.dense_rate_iters)
+        prm.g_tol = 0.0
+        prm.ftol = 0.0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.pecc_gbo_kbatch_bfgs_descend(d, x, bo, 1, 0, 1000, prm.c(), res_b, ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        it = P.results(res_b)["iters"].astype(np.int64)
+        mat = 2000 * 2000 * 4
+        byts = float(np.maximum(2 * it - 5, 0).sum()) * mat
+        busy = min(B, torch.cuda.get_device_properties(dev).multi_processor_count)
+        out[str(B)] = {"starts": B, "outer_iters_min": int(it.min()), "outer_iters_max": int(it.max()),
+                       "kernel_ms": ms, "matrix_bytes": byts, "GBs": byts / ms / 1e6,
+                       "busy_cus": busy, "GBs_per_busy_cu": byts / ms / 1e6 / busy}
+        print(f"[bench] dense k=1 matrix pass, {B} starts x {int(it.max())} outer iterations: "
+              f"{ms:.1f} ms, {byts / ms / 1e9:.3f} TB/s, {byts / ms / 1e6 / busy:.1f} GB/s per CU",
+              file=sys.stderr, flush=True)
+        del ws
+    return out
 
 
 def parse(argv=None):
@@ -214,6 +262,8 @@ def parse(argv=None):
     ap.add_argument("--kbatch-dense-ks", default="1,2,5,6,10", help="batch counts, dense matrices")
     ap.add_argument("--kbatch-dense-instances", type=int, default=256,
                     help="random starts of the dense-matrix study (0: skip)")
+    ap.add_argument("--dense-rate-iters", type=int, default=200,
+                    help="outer iterations of the fixed-length dense k = 1 throughput runs (0: skip)")
     ap.add_argument("--kbatch-instances", type=int, default=512,
                     help="random starts per setting (more than the CUs: the rate reflects the mean)")
     ap.add_argument("--sed-iters", type=int, default=10, help="SED iterations of the chains")

@@ -339,14 +339,15 @@ int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t
 }
 
 namespace {
-// floats of matrix storage per instance for batches of at most max_batch
-// circles: sum_p d_p^2 <= (2 max_batch) sum_p d_p <= 4 max_batch max_n
+// floats of storage per instance for batches of at most max_batch circles:
+// the matrices, d_p = 2|B_p| rows of d_p rounded up to a multiple of 4
+// floats, sum_p d_p (d_p + 2) <= (2 max_batch + 2) sum_p d_p <= 4 max_batch
+// max_n + 4 max_n, and four vectors of d_p floats per batch (8 max_n); a
+// multiple of 4 floats, so every instance's region stays 16-byte aligned
 int64_t dense_stride(const pecc_instances *inst, int32_t max_batch)
 {
-    // the matrices (sum of (2|B_p|)^2 <= 4 max_batch n) and four vectors of
-    // 2|B_p| floats per batch (8 n)
     const int64_t n = inst->max_n > 0 ? inst->max_n : 1;
-    return 4 * (int64_t)max_batch * n + 8 * n;
+    return 4 * (int64_t)max_batch * n + 12 * n;
 }
 }  // namespace
 

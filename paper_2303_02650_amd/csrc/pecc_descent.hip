@@ -108,7 +108,7 @@ struct DenseShared {
     uint16_t memb[kMaxN];
     int hoff[kMaxSeqBatches + 1];
     int voff[kMaxSeqBatches + 1];
-    float vb[4][2 * kMaxN];
+    float4 vr[2 * kMaxN];       // (g, y_Q, s_K, w_K) by row of the batch matrix
     float wpart[4][kDB / kWave];
     float4 part[2 * kDB];
 };
@@ -119,150 +119,135 @@ struct DenseShared {
 enum : int { kDnIdent = 1, kDnK = 2, kDnQ = 4, kDnSlot = 8 };
 
 // Work split of a pass over a symmetric d x d matrix (d even, d <= 2048)
-// stored row-major: an item is a column pair pr (two consecutive columns,
-// one 8-byte load per row, consecutive across a wave) and a slice of the
-// rows; there are up to 2 BLOCK items and thread t streams items t and
-// t + BLOCK side by side, so every wave keeps two load streams in flight.
-struct SymSplit {
-    int cp, nq, items;
-    __device__ SymSplit(int d, int nthreads)
+// stored row-major with rows of ld = d rounded up to a multiple of 4 floats
+// (16-byte aligned rows; the padding columns d, d + 1 of a d = 2 mod 4
+// matrix belong to no entry): an item is a column quad (four consecutive
+// columns, one 16-byte load per row, consecutive across a wave) and a
+// slice of the rows; there are at most BLOCK items, one per thread.
+struct QuadSplit {
+    int cq, nq, items;
+    __device__ QuadSplit(int ld, int nthreads)
     {
-        cp = d / 2;
-        nq = cp > 0 ? 2 * nthreads / cp : 1;
+        cq = ld / 4;
+        nq = cq > 0 ? nthreads / cq : 1;
         nq = nq < 1 ? 1 : (nq > 16 ? 16 : nq);
-        items = cp * nq;
-    }
-    __device__ void item(int it, int d, int &pr, int &q0, int &q1) const
-    {
-        if (it >= items) { pr = 0; q0 = q1 = 0; return; }
-        pr = it % cp;
-        const int sl = it / cp;
-        q0 = (int)((int64_t)d * sl / nq);
-        q1 = (int)((int64_t)d * (sl + 1) / nq);
+        items = cq * nq;
     }
 };
 
-// One element pair (row r, columns 2pc and 2pc + 1) of a matrix pass:
-// h is S's pair (I's when nothing is read); the two products take S's
-// values, and with STORE h becomes S + U for the symmetric rank-2 update
-// U = -(w s' + s w') ib + a2 s s' (s0, s1, w0, w1: s and w at the two
-// columns).  v[0] = g, v[1] = y, v[2] = s, v[3] = w.
+// Row length of a dense batch matrix of order d.
+__device__ __forceinline__ int sym_ld(int d) { return (d + 3) & ~3; }
+
+// One row of a thread's column quad: h holds S's four entries of the row
+// (I's when nothing is read), vq = (g, y, s, w) at the row, cs and cw s
+// and w at the four columns.  acc[0..3] gather (S g) and acc[4..7] (S y) of
+// the four columns; with STORE h becomes S + U for the symmetric rank-2
+// update U = -(w s' + s w') ib + a2 s s'.
 template <bool STORE>
-__device__ __forceinline__ void pass_elem(float2 &h, int r, const float *const (&v)[4], float s0,
-                                          float s1, float w0, float w1, float ib, float a2,
-                                          float4 &acc)
+__device__ __forceinline__ void quad_elem(float4 &h, float4 vq, float4 cs, float4 cw, float ib,
+                                          float a2, float (&acc)[8])
 {
-    const float gq = v[0][r], yq = v[1][r];
-    acc.x += h.x * gq;
-    acc.y += h.y * gq;
-    acc.z += h.x * yq;
-    acc.w += h.y * yq;
+    acc[0] += h.x * vq.x;
+    acc[1] += h.y * vq.x;
+    acc[2] += h.z * vq.x;
+    acc[3] += h.w * vq.x;
+    acc[4] += h.x * vq.y;
+    acc[5] += h.y * vq.y;
+    acc[6] += h.z * vq.y;
+    acc[7] += h.w * vq.y;
     if constexpr (STORE) {
-        const float sq_ = v[2][r], wq = v[3][r];
-        h.x = h.x - (wq * s0 + sq_ * w0) * ib + a2 * sq_ * s0;
-        h.y = h.y - (wq * s1 + sq_ * w1) * ib + a2 * sq_ * s1;
+        h.x = h.x - (vq.w * cs.x + vq.z * cw.x) * ib + a2 * vq.z * cs.x;
+        h.y = h.y - (vq.w * cs.y + vq.z * cw.y) * ib + a2 * vq.z * cs.y;
+        h.z = h.z - (vq.w * cs.z + vq.z * cw.z) * ib + a2 * vq.z * cs.z;
+        h.w = h.w - (vq.w * cs.w + vq.z * cw.w) * ib + a2 * vq.z * cs.w;
     }
 }
 
 template <bool LOAD>
-__device__ __forceinline__ float2 pass_load(const float2 *col, int64_t st, int rr, int r, int pc)
+__device__ __forceinline__ float4 quad_load(const float4 *col, int64_t st, int rr, int r, int c0)
 {
     if constexpr (LOAD) return col[(int64_t)rr * st];
-    else return make_float2(r == 2 * pc ? 1.f : 0.f, r == 2 * pc + 1 ? 1.f : 0.f);
+    else
+        return make_float4(r == c0 ? 1.f : 0.f, r == c0 + 1 ? 1.f : 0.f, r == c0 + 2 ? 1.f : 0.f,
+                           r == c0 + 3 ? 1.f : 0.f);
 }
 
-// Rows [q, q + len) of column pair pc (col points at row q): batches of 8
-// independent loads, the arithmetic in ascending rows, then the stores.
-template <bool LOAD, bool STORE>
-__device__ __forceinline__ void col_pass(float2 *__restrict__ col, int64_t st, int q, int len,
-                                         int pc, const float *const (&v)[4], float ib, float a2,
-                                         float4 &acc)
-{
-    const float s0 = v[2][2 * pc], s1 = v[2][2 * pc + 1], w0 = v[3][2 * pc], w1 = v[3][2 * pc + 1];
-    int r = 0;
-    for (; r + 8 <= len; r += 8) {
-        float2 h[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) h[u] = pass_load<LOAD>(col, st, r + u, q + r + u, pc);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) pass_elem<STORE>(h[u], q + r + u, v, s0, s1, w0, w1, ib, a2, acc);
-        if constexpr (STORE) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) col[(int64_t)(r + u) * st] = h[u];
-        }
-    }
-    for (; r < len; ++r) {
-        float2 h = pass_load<LOAD>(col, st, r, q + r, pc);
-        pass_elem<STORE>(h, q + r, v, s0, s1, w0, w1, ib, a2, acc);
-        if constexpr (STORE) col[(int64_t)r * st] = h;
-    }
-}
-
-// One pass over a symmetric d x d matrix S (d even, 8-byte aligned, row-
-// major): S g and S y as column sums (y_r = sum_q S[q][r] v[q] in ascending
-// q per row slice, slices added in order: deterministic) into part[r / 2]
-// = ((S g)_{2k}, (S g)_{2k+1}, (S y)_{2k}, (S y)_{2k+1}) for k < d / 2, and
-// with STORE S + U written back (U as in pass_elem, with ib and a2).
-// LOAD = false takes S = I without reading it.  part holds 2 BLOCK
-// entries; every thread of the block calls it; ends with a barrier.
+// One pass over a symmetric d x d matrix S (rows of sym_ld(d) floats,
+// 16-byte aligned): S g and S y as column sums (y_c = sum_r S[r][c] v[r] in
+// ascending r per row slice, slices added in order: deterministic) into
+// part[k] = ((S g)_{2k}, (S g)_{2k+1}, (S y)_{2k}, (S y)_{2k+1}) for k <
+// d / 2, and with STORE S + U written back (U as in quad_elem, with ib and
+// a2).  vr[r] = (g, y, s, w) at row r.  LOAD = false takes S = I without
+// reading it.  The row loop keeps U loads of 16 bytes in flight per thread
+// before it waits.  part holds 2 BLOCK entries; every thread of the block
+// calls it; ends with a barrier.
 template <int BLOCK, bool LOAD, bool STORE>
-__device__ void sym_pass(float *__restrict__ H, int d, const float *const (&v)[4], float ib,
+__device__ void sym_pass(float *__restrict__ H, int d, const float4 *__restrict__ vr, float ib,
                          float a2, float4 *part)
 {
+    constexpr int U = 8;
     const int t = (int)threadIdx.x;
-    const SymSplit sp(d, BLOCK);
-    float2 *H2 = reinterpret_cast<float2 *>(H);
-    int pa, qa0, qa1, pb, qb0, qb1;
-    sp.item(t, d, pa, qa0, qa1);
-    sp.item(t + BLOCK, d, pb, qb0, qb1);
-    const int La = qa1 - qa0, Lb = qb1 - qb0;
-    const int64_t st = sp.cp;
-    float2 *ca = H2 + (int64_t)qa0 * st + pa, *cb = H2 + (int64_t)qb0 * st + pb;
-    const float sa0 = v[2][2 * pa], sa1 = v[2][2 * pa + 1], wa0 = v[3][2 * pa], wa1 = v[3][2 * pa + 1];
-    const float sb0 = v[2][2 * pb], sb1 = v[2][2 * pb + 1], wb0 = v[3][2 * pb], wb1 = v[3][2 * pb + 1];
-    float4 accA = make_float4(0.f, 0.f, 0.f, 0.f), accB = accA;
-    // both streams side by side while both have rows, U loads each in flight
-    // (8 for a read-only pass; 4 when the pass also writes, which needs the
-    // rank-2 operands of both streams in registers)
-    constexpr int U = STORE ? 4 : 8;
-    const int L2 = La < Lb ? La : Lb;
-    int r = 0;
-    for (; r + U <= L2; r += U) {
-        float2 ha[U], hb[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            ha[u] = pass_load<LOAD>(ca, st, r + u, qa0 + r + u, pa);
-            hb[u] = pass_load<LOAD>(cb, st, r + u, qb0 + r + u, pb);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            pass_elem<STORE>(ha[u], qa0 + r + u, v, sa0, sa1, wa0, wa1, ib, a2, accA);
-            pass_elem<STORE>(hb[u], qb0 + r + u, v, sb0, sb1, wb0, wb1, ib, a2, accB);
-        }
-        if constexpr (STORE) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                ca[(int64_t)(r + u) * st] = ha[u];
-                cb[(int64_t)(r + u) * st] = hb[u];
-            }
+    const int ld = sym_ld(d);
+    const QuadSplit sp(ld, BLOCK);
+    const bool on = t < sp.items;
+    const int qd = on ? t % sp.cq : 0, sl = on ? t / sp.cq : 0;
+    const int q0 = on ? (int)((int64_t)d * sl / sp.nq) : 0;
+    const int q1 = on ? (int)((int64_t)d * (sl + 1) / sp.nq) : 0;
+    const int c0 = 4 * qd;
+    const int64_t st = ld / 4;
+    float4 *col = reinterpret_cast<float4 *>(H) + (int64_t)q0 * st + qd;
+    // s and w at the quad's columns (zero at padding columns)
+    float4 cs = make_float4(0.f, 0.f, 0.f, 0.f), cw = cs;
+    if (on) {
+        const float4 v0 = vr[c0], v1 = vr[c0 + 1];
+        cs.x = v0.z;
+        cw.x = v0.w;
+        cs.y = v1.z;
+        cw.y = v1.w;
+        if (c0 + 2 < d) {
+            const float4 v2 = vr[c0 + 2], v3 = vr[c0 + 3];
+            cs.z = v2.z;
+            cw.z = v2.w;
+            cs.w = v3.z;
+            cw.w = v3.w;
         }
     }
-    col_pass<LOAD, STORE>(ca + (int64_t)r * st, st, qa0 + r, La - r, pa, v, ib, a2, accA);
-    col_pass<LOAD, STORE>(cb + (int64_t)r * st, st, qb0 + r, Lb - r, pb, v, ib, a2, accB);
-    if (t < sp.items) part[t] = accA;
-    if (t + BLOCK < sp.items) part[t + BLOCK] = accB;
-    __syncthreads();
-    // slice sums in place: entry k < cp is read and written by one thread only
-    for (int k = t; k < sp.cp; k += BLOCK) {
-        float4 acc = part[k];
-        for (int j = 1; j < sp.nq; ++j) {
-            const float4 o = part[j * sp.cp + k];
-            acc.x += o.x;
-            acc.y += o.y;
-            acc.z += o.z;
-            acc.w += o.w;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int L = q1 - q0;
+    int r = 0;
+    for (; r + U <= L; r += U) {
+        float4 h[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) h[u] = quad_load<LOAD>(col, st, r + u, q0 + r + u, c0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) quad_elem<STORE>(h[u], vr[q0 + r + u], cs, cw, ib, a2, acc);
+        if constexpr (STORE) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) col[(int64_t)(r + u) * st] = h[u];
         }
-        part[k] = acc;
+    }
+    for (; r < L; ++r) {
+        float4 h = quad_load<LOAD>(col, st, r, q0 + r, c0);
+        quad_elem<STORE>(h, vr[q0 + r], cs, cw, ib, a2, acc);
+        if constexpr (STORE) col[(int64_t)r * st] = h;
+    }
+    const int cpl = ld / 2;
+    if (on) {
+        part[sl * cpl + 2 * qd] = make_float4(acc[0], acc[1], acc[4], acc[5]);
+        part[sl * cpl + 2 * qd + 1] = make_float4(acc[2], acc[3], acc[6], acc[7]);
+    }
+    __syncthreads();
+    // slice sums in place: entry k < d / 2 is read and written by one thread only
+    for (int k = t; k < d / 2; k += BLOCK) {
+        float4 a = part[k];
+        for (int j = 1; j < sp.nq; ++j) {
+            const float4 o = part[j * cpl + k];
+            a.x += o.x;
+            a.y += o.y;
+            a.z += o.z;
+            a.w += o.w;
+        }
+        part[k] = a;
     }
     __syncthreads();
 }
@@ -425,7 +410,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 for (int q = 0; q < A.nbat; ++q) {
                     sq.hoff[q] = o;
                     const int d = 2 * sq.cnt[q];
-                    o += d * d;
+                    o += d * sym_ld(d);
                 }
                 sq.hoff[A.nbat] = o;
                 for (int q = 0; q < A.nbat; ++q) {
@@ -618,22 +603,15 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         const float2 yv = hasQ ? yQ[m] : z2;
                         const float2 sv = hasK ? sK[m] : z2;
                         const float2 wvv = hasK ? wK[m] : z2;
-                        sq.vb[0][2 * m] = g[c].x;
-                        sq.vb[0][2 * m + 1] = g[c].y;
-                        sq.vb[1][2 * m] = yv.x;
-                        sq.vb[1][2 * m + 1] = yv.y;
-                        sq.vb[2][2 * m] = sv.x;
-                        sq.vb[2][2 * m + 1] = sv.y;
-                        sq.vb[3][2 * m] = wvv.x;
-                        sq.vb[3][2 * m + 1] = wvv.y;
+                        sq.vr[2 * m] = make_float4(g[c].x, yv.x, sv.x, wvv.x);
+                        sq.vr[2 * m + 1] = make_float4(g[c].y, yv.y, sv.y, wvv.y);
                     }
                 }
                 __syncthreads();
-                const float *const vv[4] = {sq.vb[0], sq.vb[1], sq.vb[2], sq.vb[3]};
                 const bool pass = !ident || hasK;
-                if (ident && hasK) sym_pass<kDB, false, true>(H, d, vv, ibK, a2K, sq.part);
-                else if (hasK) sym_pass<kDB, true, true>(H, d, vv, ibK, a2K, sq.part);
-                else if (pass) sym_pass<kDB, true, false>(H, d, vv, ibK, a2K, sq.part);
+                if (ident && hasK) sym_pass<kDB, false, true>(H, d, sq.vr, ibK, a2K, sq.part);
+                else if (hasK) sym_pass<kDB, true, true>(H, d, sq.vr, ibK, a2K, sq.part);
+                else if (pass) sym_pass<kDB, true, false>(H, d, sq.vr, ibK, a2K, sq.part);
                 // S g, S y_Q of this thread's circles; K's dot products
                 float2 Hg[kCPT], wq[kCPT];
                 float4 dk = make_float4(0.f, 0.f, 0.f, 0.f);   // s_K'g, w_K'g, s_K'y_Q, w_K'y_Q
@@ -643,7 +621,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     const int i = t0 + c * kDB;
                     if (act[c] && batc_of(c) == cb) {
                         const int m = sq.memb[i];
-                        const float2 yv = make_float2(sq.vb[1][2 * m], sq.vb[1][2 * m + 1]);
+                        const float2 yv = make_float2(sq.vr[2 * m].y, sq.vr[2 * m + 1].y);
                         if (pass) {
                             const float4 pr = sq.part[m];
                             Hg[c] = make_float2(pr.x, pr.y);
@@ -652,8 +630,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                             Hg[c] = g[c];
                             wq[c] = yv;
                         }
-                        const float2 sv = make_float2(sq.vb[2][2 * m], sq.vb[2][2 * m + 1]);
-                        const float2 wvv = make_float2(sq.vb[3][2 * m], sq.vb[3][2 * m + 1]);
+                        const float2 sv = make_float2(sq.vr[2 * m].z, sq.vr[2 * m + 1].z);
+                        const float2 wvv = make_float2(sq.vr[2 * m].w, sq.vr[2 * m + 1].w);
                         dk.x += sv.x * g[c].x + sv.y * g[c].y;
                         dk.y += wvv.x * g[c].x + wvv.y * g[c].y;
                         dk.z += sv.x * yv.x + sv.y * yv.y;
@@ -668,8 +646,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         const int i = t0 + c * kDB;
                         if (act[c] && batc_of(c) == cb) {
                             const int m = sq.memb[i];
-                            const float2 sv = make_float2(sq.vb[2][2 * m], sq.vb[2][2 * m + 1]);
-                            const float2 wvv = make_float2(sq.vb[3][2 * m], sq.vb[3][2 * m + 1]);
+                            const float2 sv = make_float2(sq.vr[2 * m].z, sq.vr[2 * m + 1].z);
+                            const float2 wvv = make_float2(sq.vr[2 * m].w, sq.vr[2 * m + 1].w);
                             Hg[c].x += -(wvv.x * dk.x + sv.x * dk.y) * ibK + a2K * sv.x * dk.x;
                             Hg[c].y += -(wvv.y * dk.x + sv.y * dk.y) * ibK + a2K * sv.y * dk.x;
                             wq[c].x += -(wvv.x * dk.z + sv.x * dk.w) * ibK + a2K * sv.x * dk.z;
@@ -689,7 +667,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         const int i = t0 + c * kDB;
                         if (act[c] && batc_of(c) == cb) {
                             const int m = sq.memb[i];
-                            const float2 yv = make_float2(sq.vb[1][2 * m], sq.vb[1][2 * m + 1]);
+                            const float2 yv = make_float2(sq.vr[2 * m].y, sq.vr[2 * m + 1].y);
                             sqv[c] = sQ[m];
                             dq.x += yv.x * wq[c].x + yv.y * wq[c].y;
                             dq.y += sqv[c].x * g[c].x + sqv[c].y * g[c].y;

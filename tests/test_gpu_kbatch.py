@@ -286,12 +286,17 @@ def test_dense_descents_reach_oracle_outcomes(P):
 
 
 def test_dense_workspace_bound(P):
+    # per instance 4 max_batch max_n + 12 max_n floats; two batches of 10
+    # circles (d = 20, rows of 20 floats) need 2 (20 * 20 + 4 * 20) = 960,
+    # which max_batch = 9 gives exactly and max_batch = 8 (880) does not
     inst = synth.C1()
-    bo = host_partition(inst, "sector", 2)                    # batches of 10
-    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=9)
+    bo = host_partition(inst, "sector", 2)
+    assert sorted(np.bincount(bo, minlength=2).tolist()) == [10, 10]
+    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=8)
     assert P.STATUS[res["status"][0]] == "BAD_INSTANCE"
-    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=10)
-    assert P.STATUS[res["status"][0]] != "BAD_INSTANCE"
+    for mb in (9, 10):
+        _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=mb)
+        assert P.STATUS[res["status"][0]] != "BAD_INSTANCE"
 
 
 def test_dense_with_anm_follows_oracle_early(P):
