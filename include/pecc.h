@@ -357,6 +357,23 @@ int pecc_verify(const pecc_instances *inst, const float *xy, double tol,
                 int32_t *feasible, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * The smallest FP32 container radius of each layout (the radius that the
+ * framework of Alg. 4 records), from the same FP64 enumeration as
+ * pecc_verify.  rho_max = max_i fl(|c_i| + 1) in FP64; at any radius
+ * R >= rho_max every containment term of Eq. 2 vanishes, so the unit
+ * circles fit exactly when their pair energy is below tol.  Per instance:
+ * R_out[b] = rho_max rounded up to an FP32 value when the pair energy is
+ * below tol and that value is below the instance's radius (R64 when given,
+ * else R), otherwise R[b]; feasible[b] = 1 when the layout is feasible
+ * (E < tol) at radius R_out[b].  An instance with no circles keeps R[b];
+ * one with a non-finite coordinate keeps R[b] with feasible 0.
+ * R_out: device float [B]; feasible: device int32 [B]; both required.
+ * Errors: PECC_ERR_INVALID for a NULL output, or xy NULL with circles.
+ * ------------------------------------------------------------------------ */
+int pecc_verify_tighten(const pecc_instances *inst, const float *xy, double tol, float *R_out,
+                        int32_t *feasible, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Container adjustment (Sec. 4.2, Eq. 12, Alg. 2): the radius becomes a
  * variable and U(z, lambda) = E + lambda R^2 is minimised over z = (x, R),
  * `rounds` times (35 in the paper) with lambda halved after each round from

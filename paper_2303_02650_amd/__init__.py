@@ -83,6 +83,8 @@ _sig = {
                                              _P(pecc_descent_params), C.c_void_p, C.c_void_p]),
     "pecc_verify": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pecc_verify_tighten": (C.c_int, [_P(pecc_instances), C.c_void_p, C.c_double, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]),
     "pecc_gbo_descend_workspace_size": (C.c_int, [_P(pecc_instances), C.c_int32, _P(C.c_size_t)]),
     "pecc_gbo_descend": (C.c_int, [_P(pecc_instances), C.c_void_p, _P(pecc_descent_params),
                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
@@ -233,6 +235,11 @@ def pecc_gbo_descend(inst, xy, params: pecc_descent_params, blocks, sweep_fp64, 
 def pecc_verify(inst, xy, tol, energy64, max_pair, max_cont, feasible, stream=None):
     _check(_lib.pecc_verify(C.byref(inst.c()), _ptr(xy), float(tol), _ptr(energy64),
                             _ptr(max_pair), _ptr(max_cont), _ptr(feasible), _stream(stream)))
+
+
+def pecc_verify_tighten(inst, xy, tol, R_out, feasible, stream=None):
+    _check(_lib.pecc_verify_tighten(C.byref(inst.c()), _ptr(xy), float(tol), _ptr(R_out),
+                                    _ptr(feasible), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -456,6 +456,20 @@ int pecc_verify(const pecc_instances *inst, const float *xy, double tol, double 
                      fn);
 }
 
+int pecc_verify_tighten(const pecc_instances *inst, const float *xy, double tol, float *R_out,
+                        int32_t *feasible, hipStream_t stream)
+{
+    const char *fn = "pecc_verify_tighten";
+    int rc = check_inst(inst, fn);
+    if (rc) return rc;
+    if (!R_out || !feasible) return fail(PECC_ERR_INVALID, "%s: R_out and feasible must be set", fn);
+    if (inst->total_n > 0 && !xy) return fail(PECC_ERR_INVALID, "%s: xy is NULL", fn);
+    return check_hip(pecc::launch_verify_tighten(inst->offset, inst->R, inst->R64, xy,
+                                                 inst->num_instances, inst->total_n, tol, R_out,
+                                                 feasible, stream),
+                     fn);
+}
+
 // ---------------------------------------------------------------------------
 // Learned proposal
 // ---------------------------------------------------------------------------

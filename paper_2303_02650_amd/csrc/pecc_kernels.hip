@@ -752,6 +752,13 @@ __global__ __launch_bounds__(kHalfBlock) __attribute__((amdgpu_waves_per_eu(8, 8
 // a row, so partner i + t needs no wrap.  512 threads per instance, partner
 // positions read four at a time so that LDS latency overlaps.  No
 // contraction: products and sums round as written, like the oracle's.
+// With R_tight set it also forms the smallest container of the unit
+// circles, rho_max = max_i fl(|c_i| + 1): at any radius R >= rho_max every
+// containment term (fl(|c_i| + 1) - R) is <= 0, so the layout is feasible
+// there exactly when its pair energy is below tol.  R_tight[b] receives
+// rho_max rounded up to FP32 when that holds and the value is below the
+// instance's radius, else the instance's FP32 radius; feas_tight[b] is
+// feasibility at R_tight[b].
 // ---------------------------------------------------------------------------
 constexpr int kVerifyBlock = 512;
 
@@ -759,7 +766,8 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     const int32_t *__restrict__ offset, const float *__restrict__ R,
     const double *__restrict__ R64, const float *__restrict__ xy, int64_t total_n, double tol,
     double *__restrict__ energy64, double *__restrict__ max_pair,
-    double *__restrict__ max_cont, int32_t *__restrict__ feasible)
+    double *__restrict__ max_cont, int32_t *__restrict__ feasible, float *__restrict__ R_tight,
+    int32_t *__restrict__ feas_tight)
 {
 #pragma clang fp contract(off)
     __shared__ float2 pos[2 * kMaxN];
@@ -769,10 +777,12 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     int off, n;
     if (!instance_range(offset, b, total_n, &off, &n)) {
         if (threadIdx.x == 0) {
-            energy64[b] = __builtin_nan("");
+            if (energy64) energy64[b] = __builtin_nan("");
             if (max_pair) max_pair[b] = __builtin_nan("");
             if (max_cont) max_cont[b] = __builtin_nan("");
             if (feasible) feasible[b] = 0;
+            if (R_tight) R_tight[b] = R[b];
+            if (feas_tight) feas_tight[b] = 0;
         }
         return;
     }
@@ -786,7 +796,7 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     }
     __syncthreads();
     const double Rb = R64 ? R64[b] : (double)R[b];
-    double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0;
+    double sp = 0.0, sc = 0.0, mp = 0.0, mc = 0.0, rm = 0.0;
     const int half = (n - 1) / 2;
     const bool even = (n & 1) == 0;
     for (int i = threadIdx.x; i < n; i += kVerifyBlock) {
@@ -815,6 +825,7 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
         }
         for (; t <= cnt; ++t) pair(pos[i + t]);
         const double rho = sqrt(xi * xi + yi * yi);
+        rm = fmax(rm, rho + 1.0);
         const double d0 = (rho + 1.0) - Rb;
         if (d0 > 0.0) {
             sc = sc + d0 * d0;
@@ -826,13 +837,20 @@ __global__ __launch_bounds__(kVerifyBlock) void verify_kernel(
     const double Ec = block_sum<kVerifyBlock>(sc, sum_tmp);
     const double Mp = block_max<kVerifyBlock>(mp, sum_tmp);
     const double Mc = block_max<kVerifyBlock>(mc, sum_tmp);
+    const double Rm = R_tight ? block_max<kVerifyBlock>(rm, sum_tmp) : 0.0;
     if (threadIdx.x == 0) {
         const double E = Ep + Ec;
         const bool bad = E != E;     // a non-finite coordinate
-        energy64[b] = E;
+        if (energy64) energy64[b] = E;
         if (max_pair) max_pair[b] = bad ? E : Mp;
         if (max_cont) max_cont[b] = bad ? E : Mc;
         if (feasible) feasible[b] = E < tol ? 1 : 0;
+        if (R_tight) {
+            const float rt = __double2float_ru(Rm);     // smallest FP32 value >= Rm
+            const bool use = !bad && n > 0 && Ep < tol && (double)rt < Rb;
+            R_tight[b] = use ? rt : R[b];
+            if (feas_tight) feas_tight[b] = (use || E < tol) ? 1 : 0;
+        }
     }
 }
 
@@ -881,7 +899,17 @@ hipError_t launch_verify(const int32_t *offset, const float *R, const double *R6
                          const float *xy, int B, int64_t total_n, double tol, double *e64,
                          double *mp, double *mc, int32_t *feas, hipStream_t s)
 {
-    verify_kernel<<<B, kVerifyBlock, 0, s>>>(offset, R, R64, xy, total_n, tol, e64, mp, mc, feas);
+    verify_kernel<<<B, kVerifyBlock, 0, s>>>(offset, R, R64, xy, total_n, tol, e64, mp, mc, feas,
+                                             nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify_tighten(const int32_t *offset, const float *R, const double *R64,
+                                 const float *xy, int B, int64_t total_n, double tol,
+                                 float *R_out, int32_t *feas, hipStream_t s)
+{
+    verify_kernel<<<B, kVerifyBlock, 0, s>>>(offset, R, R64, xy, total_n, tol, nullptr, nullptr,
+                                             nullptr, nullptr, R_out, feas);
     return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ hipError_t launch_energy_grad(const int32_t *offset, const float *R, const float
 hipError_t launch_verify(const int32_t *offset, const float *R, const double *R64,
                          const float *xy, int B, int64_t total_n, double tol, double *e64,
                          double *mp, double *mc, int32_t *feas, hipStream_t s);
+hipError_t launch_verify_tighten(const int32_t *offset, const float *R, const double *R64,
+                                 const float *xy, int B, int64_t total_n, double tol,
+                                 float *R_out, int32_t *feas, hipStream_t s);
 
 // Descent constants as the kernels use them (derived from the public params).
 struct DescentArgs {

@@ -14,10 +14,9 @@ R_b.  It only sequences library calls and keeps the best record:
 
 Every adjusted radius is then tightened in FP64: the descents work on
 circles of radius 1 + contact_margin, so R' keeps up to that margin of
-slack; the smallest container of the layout's unit circles is
-max_i |c_i| + 1 (pecc_verify at radius 0 reports it as the largest
-containment overlap), rounded up to an FP32 value, and it replaces R' where
-the unit circles are pairwise overlap-free in FP64 at it.
+slack; the smallest container of the layout's unit circles,
+max_i |c_i| + 1 rounded up to an FP32 value, replaces R' where the unit
+circles are pairwise overlap-free in FP64 (pecc_verify_tighten).
 
 The random layouts are drawn here with numpy (chain c, round t: a PCG64
 stream seeded by (seed, t, c)) and passed to the library as inputs; SED
@@ -32,7 +31,7 @@ import numpy as np
 import torch
 
 from . import (DescentParams, DeviceInstances, RESULT_DTYPE, adjust_container,
-               pecc_lbfgs_descend, pecc_lbfgs_descend_workspace_size, verify)
+               pecc_lbfgs_descend, pecc_lbfgs_descend_workspace_size, pecc_verify_tighten)
 from .sed import SedChains
 
 
@@ -72,31 +71,21 @@ class Framework:
     def _instances(self, R: np.ndarray) -> DeviceInstances:
         return DeviceInstances.from_host(self.offset, np.asarray(R, dtype=np.float32))
 
-    def _verify_at(self, x: torch.Tensor, R: torch.Tensor):
-        off = torch.from_numpy(self.offset).to(self.dev)
-        inst = DeviceInstances(offset=off, R=R.float().contiguous(), R64=R.double().contiguous(),
-                               max_n=self.n, total_n=self.C * self.n)
-        return verify(inst, x)
-
-    def _feasible_at(self, x: torch.Tensor, R: torch.Tensor) -> np.ndarray:
-        """Unit circles overlap-free (FP64 E < 1e-20) at the FP32 radii R."""
-        return self._verify_at(x, R)[3].cpu().numpy().astype(bool)
-
     def _tighten(self, x: torch.Tensor, R_adj: torch.Tensor):
-        """Adjusted radii and their FP64 feasibility, each radius replaced by
-        the FP32 value just above max_i |c_i| + 1 where the unit circles
-        are overlap-free in FP64 at that value and it is smaller."""
-        Ra = R_adj.cpu().numpy().astype(np.float64)
-        ok = self._feasible_at(x, R_adj)
-        zero = torch.zeros(self.C, dtype=torch.float64, device=self.dev)
-        Rmin = self._verify_at(x, zero)[2].cpu().numpy()          # max_i fl(|c_i| + 1)
-        Rt = Rmin.astype(np.float32)
-        up = Rt.astype(np.float64) < Rmin
-        Rt[up] = np.nextafter(Rt[up], np.float32(np.inf))
-        ok_t = self._feasible_at(x, torch.from_numpy(Rt).to(self.dev))
-        use = ok_t & (Rt.astype(np.float64) < Ra)
-        self.tightened += int(use.sum())
-        return np.where(use, Rt.astype(np.float64), Ra), ok | use
+        """Each adjusted radius replaced by the smallest FP32 container of
+        the layout's unit circles (max_i |c_i| + 1 rounded up) where they are
+        pairwise overlap-free in FP64 and it is smaller, with FP64
+        feasibility at the returned radius (pecc_verify_tighten)."""
+        off = torch.from_numpy(self.offset).to(self.dev)
+        Rf = R_adj.float().contiguous()
+        inst = DeviceInstances(offset=off, R=Rf, R64=Rf.double(), max_n=self.n,
+                               total_n=self.C * self.n)
+        R_out = torch.empty(self.C, dtype=torch.float32, device=self.dev)
+        feas = torch.empty(self.C, dtype=torch.int32, device=self.dev)
+        pecc_verify_tighten(inst, x, 1e-20, R_out, feas)
+        Rn = R_out.cpu().numpy().astype(np.float64)
+        self.tightened += int((Rn < Rf.cpu().numpy().astype(np.float64)).sum())
+        return Rn, feas.cpu().numpy().astype(bool)
 
     def step(self) -> dict:
         """One round of Alg. 4 for every chain."""

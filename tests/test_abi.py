@@ -117,6 +117,10 @@ def test_build_and_sweep_validation(P):
     assert call(full=2, col=C.c_void_p(0x31)) == -1
     # verify
     assert P._lib.pecc_verify(C.byref(inst), C.c_void_p(0x10), 1e-20, None, None, None, None, None) == -1
+    vt = P._lib.pecc_verify_tighten
+    assert vt(C.byref(inst), C.c_void_p(0x10), 1e-20, None, C.c_void_p(0x70), None) == -1
+    assert vt(C.byref(inst), C.c_void_p(0x10), 1e-20, C.c_void_p(0x70), None, None) == -1
+    assert vt(C.byref(inst), None, 1e-20, C.c_void_p(0x70), C.c_void_p(0x80), None) == -1
 
 
 def test_default_params_match_header(P):

@@ -280,6 +280,54 @@ def test_verify_closed_forms(P):
     assert f[0] == 1 and f[3] == 0
 
 
+def _tight_expected(xy, R):
+    """Smallest FP32 container of FP32 positions by the oracle: rho_max =
+    max_i fl(|c_i| + 1) (the oracle's containment overlap at radius 0),
+    rounded up to FP32; taken when the unit circles fit there (oracle FP64
+    check) and it is below R."""
+    if len(xy) == 0:
+        return np.float32(R), oracle.verify(xy, R)["feasible"]
+    rho = oracle.verify(xy, 0.0)["max_cont_overlap"]
+    rt = np.float32(rho)
+    if float(rt) < rho:
+        rt = np.nextafter(rt, np.float32(np.inf))
+    assert float(rt) >= rho and float(np.nextafter(rt, np.float32(0))) < rho
+    if float(rt) < R and oracle.verify(xy, float(rt))["feasible"]:
+        return rt, True
+    return np.float32(R), oracle.verify(xy, R)["feasible"]
+
+
+def test_verify_tighten_gives_smallest_fp32_container(P):
+    import math
+    s = 1 + 1e-6
+    hexa = np.array([[0, 0]] + [[2 * s * math.cos(k * math.pi / 3), 2 * s * math.sin(k * math.pi / 3)]
+                                for k in range(6)])
+    g = np.array([[2.5 * i - 5.0, 2.5 * j - 5.0] for i in range(5) for j in range(5)])
+    rng = synth.rng_for(11)
+    g = g + rng.uniform(-0.2, 0.2, size=g.shape)               # pairwise >= 2.1 apart
+    pair_over = np.array([[-0.9, 0.0], [0.9, 0.0]])            # overlapping
+    bad = np.array([[0.0, 0.0], [np.inf, 0.0]])
+    layouts = [(hexa, 3.01), (hexa, 2.9), (g, 12.0), (pair_over, 3.0), (np.zeros((0, 2)), 1.5),
+               (np.array([[-1.000001, 0.0], [1.000001, 0.0]]), 2.5), (bad, 4.0)]
+    inst = synth.pack([xy for xy, _ in layouts], [R for _, R in layouts])
+    d, xy = to_dev(P, inst)
+    R_out = torch.empty(inst.B, dtype=torch.float32, device="cuda")
+    feas = torch.empty(inst.B, dtype=torch.int32, device="cuda")
+    P.pecc_verify_tighten(d, xy, 1e-20, R_out, feas)
+    Ro, fo = R_out.cpu().numpy(), feas.cpu().numpy()
+    for b in range(inst.B - 1):
+        rt, ok = _tight_expected(inst.instance(b), float(inst.R[b]))
+        assert Ro[b] == rt, (b, Ro[b], rt)
+        assert bool(fo[b]) == ok, b
+        assert bool(fo[b]) == oracle.verify(inst.instance(b), float(Ro[b]))["feasible"], b
+    assert Ro[-1] == np.float32(4.0) and fo[-1] == 0          # a non-finite coordinate
+    # tightened: the hexagon at 3.01, the grid, the spaced pair; kept: the rest
+    assert Ro[0] < np.float32(3.01) and Ro[2] < 12.0 and Ro[5] < 2.5
+    assert Ro[1] == np.float32(2.9) and fo[1] == 0
+    assert Ro[3] == np.float32(3.0) and fo[3] == 0
+    assert Ro[4] == np.float32(1.5) and fo[4] == 1
+
+
 # ---------------------------------------------------------------------------
 # descent
 # ---------------------------------------------------------------------------
