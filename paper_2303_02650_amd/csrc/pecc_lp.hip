@@ -178,12 +178,40 @@ __device__ void load_weights(const float *__restrict__ P, NetWeights &W, bool tr
     }
 }
 
-__device__ __forceinline__ float gelu(float t) { return 0.5f * t * (1.0f + erff(t * 0.70710678118654752f)); }
+// erf(x) by the rational approximation 7.1.26 of Abramowitz and Stegun
+// (Handbook of Mathematical Functions): erf(x) = 1 - (a1 t + ... + a5 t^5)
+// exp(-x^2) with t = 1 / (1 + p x) for x >= 0, odd in x; at most 1.5e-7 from
+// erf in exact arithmetic, about 6e-7 in FP32 with the hardware reciprocal
+// and exponential.  gauss receives the exp(-x^2) it forms.  One reciprocal,
+// one exponential and seven FMAs, against the library erff's longer
+// piecewise evaluation: the network's 128 activations per row are most of
+// its vector work.
+__device__ __forceinline__ float erf_as(float x, float &gauss)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float q = fmaf(t, 1.061405429f, -1.453152027f);
+    q = fmaf(t, q, 1.421413741f);
+    q = fmaf(t, q, -0.284496736f);
+    q = fmaf(t, q, 0.254829592f);
+    gauss = __expf(-ax * ax);
+    return copysignf(fmaf(-t * q, gauss, 1.0f), x);
+}
+
+// GELU(t) = t Phi(t) = 0.5 t (1 + erf(t / sqrt 2)) and its derivative
+// Phi(t) + t phi(t), phi(t) = exp(-t^2 / 2) / sqrt(2 pi) (the same
+// exponential as the erf's).
+__device__ __forceinline__ float gelu(float t)
+{
+    float gs;
+    return 0.5f * t * (1.0f + erf_as(t * 0.70710678118654752f, gs));
+}
 
 __device__ __forceinline__ float gelu_prime(float t)
 {
-    return 0.5f * (1.0f + erff(t * 0.70710678118654752f)) +
-           t * 0.39894228040143268f * __expf(-0.5f * t * t);
+    float gs;
+    const float e = erf_as(t * 0.70710678118654752f, gs);
+    return 0.5f * (1.0f + e) + t * 0.39894228040143268f * gs;
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
