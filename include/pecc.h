@@ -445,7 +445,7 @@ int pecc_sed_select(const pecc_instances *chains, int32_t M, const int32_t *m,
  * the k best-scored distinct circles move to their candidates' points.  The
  * network is the project's addition (the paper perturbs every circle by a
  * random shift); uniform random choice is the fallback, and the descent's
- * final FP64 energy is the judge (pecc_accept).
+ * final FP64 energy decides what is kept (pecc_accept).
  * ======================================================================== */
 #define PECC_FEATURES     8     /* features per candidate                       */
 #define PECC_MLP_PARAMS   4801  /* network parameters (layout below)            */

@@ -4,7 +4,7 @@ the result when its energy is lower.  Here a perturbation relocates k = 5 %
 of the circles; a candidate is (circle i, destination q uniform in the disk
 of radius R - 1), a network scores candidates from local features and the
 k best-scored distinct circles move.  Uniform random choice among the same
-candidates is the fallback, and the descent's final FP64 energy judges.
+candidates is the fallback, and the descent's final FP64 energy decides.
 
 This module only sequences library calls; every computation runs in
 libpecc's kernels (descent, FP64 verify, features, network forward, Adam
