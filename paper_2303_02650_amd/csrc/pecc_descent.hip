@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         // ---- per-thread state (circle c of this thread is tid + c*kDB) ----
         bool act[kCPT];
         float2 x[kCPT], g[kCPT], xr[kCPT], p[kCPT];
-        float2 S[kMM][kCPT], Y[kMM][kCPT];      // curvature pairs, newest at kMM-1
+        double S[kMM][kCPT], Y[kMM][kCPT];      // curvature pairs (float2 bits), newest at kMM-1
 #pragma unroll
         for (int c = 0; c < kCPT; ++c) {
             const int i = tid + c * kDB;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             xr[c] = x[c];
             p[c] = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int j = 0; j < kMM; ++j) { S[j][c] = make_float2(0.f, 0.f); Y[j][c] = make_float2(0.f, 0.f); }
+            for (int j = 0; j < kMM; ++j) { S[j][c] = 0.0; Y[j][c] = 0.0; }
         }
         // ---- uniform state ---------------------------------------------------
         int k = 0;                     // valid pairs, slots kMM-k .. kMM-1
@@ -1501,8 +1501,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         if (push && inb[c]) {
 #pragma unroll
                             for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
-                            S[kMM - 1][c] = sc[c];
-                            Y[kMM - 1][c] = yc[c];
+                            S[kMM - 1][c] = __builtin_bit_cast(double, sc[c]);
+                            Y[kMM - 1][c] = __builtin_bit_cast(double, yc[c]);
                         }
                         x[c] = xt[c];
                         g[c] = gt[c];
@@ -1527,8 +1527,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
                         for (int j = 0; j < kMM; ++j) {
                             const float csj = sh.coef[0][j], cyj = sh.coef[1][j];
-                            px -= csj * S[j][c].x + cyj * Y[j][c].x;
-                            py -= csj * S[j][c].y + cyj * Y[j][c].y;
+                            px -= csj * as_f2(S[j][c]).x + cyj * as_f2(Y[j][c]).x;
+                            py -= csj * as_f2(S[j][c]).y + cyj * as_f2(Y[j][c]).y;
                         }
                         p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(px, py)
                                                                   : make_float2(0.f, 0.f);
@@ -1637,8 +1637,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     if (!DENSE && push && inb[c]) {
 #pragma unroll
                         for (int j = 0; j < kMM - 1; ++j) { S[j][c] = S[j + 1][c]; Y[j][c] = Y[j + 1][c]; }
-                        S[kMM - 1][c] = sc[c];
-                        Y[kMM - 1][c] = yc[c];
+                        S[kMM - 1][c] = __builtin_bit_cast(double, sc[c]);
+                        Y[kMM - 1][c] = __builtin_bit_cast(double, yc[c]);
                     }
                     x[c] = xt[c];
                     g[c] = gt[c];
@@ -1742,8 +1742,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     #pragma unroll
                         for (int j = 0; j < kMM; ++j) {
                             const float csj = lane_value(cs_v, j), cyj = lane_value(cy_v, j);
-                            px -= csj * S[j][c].x + cyj * Y[j][c].x;
-                            py -= csj * S[j][c].y + cyj * Y[j][c].y;
+                            px -= csj * as_f2(S[j][c]).x + cyj * as_f2(Y[j][c]).x;
+                            py -= csj * as_f2(S[j][c]).y + cyj * as_f2(Y[j][c]).y;
                         }
                         p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(px, py)
                                                                   : make_float2(0.f, 0.f);

@@ -72,14 +72,19 @@ __device__ __forceinline__ void store_bad_instance(DescentResultDev *out, int b)
     store_result(out, b, r, 0);
 }
 
+// History elements: float2, or the same bits held as one 64-bit value (an
+// aligned register pair, so that shifting the history moves pairs).
+__device__ __forceinline__ float2 as_f2(float2 v) { return v; }
+__device__ __forceinline__ float2 as_f2(double v) { return __builtin_bit_cast(float2, v); }
+
 // Value of reduction slot v summed over this thread's circles (v is a
 // constant after unrolling, so the branches fold away): one FMA chain over
 // the circles' coordinates, started by a product.
-template <int CPT>
+template <int CPT, typename HV>
 __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], const float2 (&sc)[CPT],
                                             const float2 (&yc)[CPT],
-                                            const float2 (&S)[kMM][CPT],
-                                            const float2 (&Y)[kMM][CPT], float e, float e1)
+                                            const HV (&S)[kMM][CPT],
+                                            const HV (&Y)[kMM][CPT], float e, float e1)
 {
     if (v == sE) return e;
     if (v == sE1) return e1;
@@ -87,12 +92,12 @@ __device__ __forceinline__ float slot_value(int v, const float2 (&gt)[CPT], cons
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         float2 a, b;
-        if (v < kMM) { a = gt[c]; b = S[v][c]; }
-        else if (v < 2 * kMM) { a = gt[c]; b = Y[v - kMM][c]; }
-        else if (v < 3 * kMM - 1) { a = sc[c]; b = S[v - 2 * kMM + 1][c]; }
-        else if (v < 4 * kMM - 2) { a = sc[c]; b = Y[v - (3 * kMM - 1) + 1][c]; }
-        else if (v < 5 * kMM - 3) { a = yc[c]; b = S[v - (4 * kMM - 2) + 1][c]; }
-        else if (v < 6 * kMM - 4) { a = yc[c]; b = Y[v - (5 * kMM - 3) + 1][c]; }
+        if (v < kMM) { a = gt[c]; b = as_f2(S[v][c]); }
+        else if (v < 2 * kMM) { a = gt[c]; b = as_f2(Y[v - kMM][c]); }
+        else if (v < 3 * kMM - 1) { a = sc[c]; b = as_f2(S[v - 2 * kMM + 1][c]); }
+        else if (v < 4 * kMM - 2) { a = sc[c]; b = as_f2(Y[v - (3 * kMM - 1) + 1][c]); }
+        else if (v < 5 * kMM - 3) { a = yc[c]; b = as_f2(S[v - (4 * kMM - 2) + 1][c]); }
+        else if (v < 6 * kMM - 4) { a = yc[c]; b = as_f2(Y[v - (5 * kMM - 3) + 1][c]); }
         else if (v == sGG) { a = gt[c]; b = gt[c]; }
         else if (v == sScSc) { a = sc[c]; b = sc[c]; }
         else if (v == sScYc) { a = sc[c]; b = yc[c]; }
@@ -237,12 +242,12 @@ __device__ __forceinline__ void swap16(float &a, float &b)
 // whose bit is set keeps the upper slot).  Slots are produced in groups of
 // eight (u + 8k, k = 0..7) that the first three stages consume, so only a
 // few values are live at once.
-template <int CPT>
+template <int CPT, typename HV>
 __device__ __forceinline__ float wave_reduce_scatter(const float2 (&gt)[CPT],
                                                      const float2 (&sc)[CPT],
                                                      const float2 (&yc)[CPT],
-                                                     const float2 (&S)[kMM][CPT],
-                                                     const float2 (&Y)[kMM][CPT], float e,
+                                                     const HV (&S)[kMM][CPT],
+                                                     const HV (&Y)[kMM][CPT], float e,
                                                      float e1)
 {
     const int lane = threadIdx.x & (kWave - 1);
