@@ -65,6 +65,7 @@ struct GboShared {
     float redf[2][kGW];
     double redd[2][kGW];
     int scan_tmp[kGW + 1];
+    int evw[kGW];                           // per-wave evaluation counts at the end
     int flag, over, bad, work;
 };
 
@@ -651,11 +652,16 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
             pair_mine = (int64_t)pm;
         }
         {
+            // every wave's batch evaluations, and those over the cell grid
             __syncthreads();
-            if (lane == 0) sh.scan_tmp[wv] = cell_mine;
+            if (lane == 0) { sh.scan_tmp[wv] = cell_mine; sh.evw[wv] = evals; }
             __syncthreads();
             cell_mine = 0;
-            for (int w = 0; w < kGW; ++w) cell_mine += sh.scan_tmp[w];
+            evals = 0;
+            for (int w = 0; w < kGW; ++w) {
+                cell_mine += sh.scan_tmp[w];
+                evals += sh.evw[w];
+            }
         }
         if (tid == 0) {
             DescentHead r;

@@ -52,6 +52,11 @@ def test_gbo_first_outer_iterations_follow_oracle(P, name, outer, fp64):
                                          oracle.DescentParams(g_tol=0.0), blocks=blocks,
                                          max_outer=outer)
         assert res["iters"][b] == r64["outer"]
+        # batch evaluations of every wave: each visit's starting point and
+        # its line-search trials, counted as the oracle counts them
+        assert res["evals"][b] >= 2 * r64["visits"]
+        assert abs(int(res["evals"][b]) - r64["evals"]) <= 2, (res["evals"][b], r64["evals"])
+        assert res["cell_evals"][b] <= res["evals"][b]
         scale = max(1.0, float(np.abs(x64).max()))
         err = np.abs(xg[o0:o1] - x64).max() / scale
         assert err < 5e-5 * outer, (name, b, err)
