@@ -46,8 +46,8 @@ DESCENT_TRAFFIC_BYTES_256 = 4.67e6
 # evaluation, SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES):
 # profiles/lbfgs_descend_kernel_sq_counters_256x1000.md.  Valid for the
 # kernel as profiled.
-DESCENT_VALU_PER_WAVE_EVAL_256 = 1215
-DESCENT_VALU_ACTIVE_SHARE_256 = 0.335
+DESCENT_VALU_PER_WAVE_EVAL_256 = 1159
+DESCENT_VALU_ACTIVE_SHARE_256 = 0.321
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 
