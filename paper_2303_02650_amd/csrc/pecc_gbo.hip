@@ -204,6 +204,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                 __syncthreads();
                 for (int i = tid; i < n; i += kGT) {
                     const float2 q = sh.pos[i];
+                    const int bi = sh.batch_of[i];
                     int m = 0;
                     const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
                     const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                         for (int t = a; t < z; ++t) {
                             const int j = sh.cell_circ[t];
                             if (j != i && near_cut(q, sh.pos[j], c2lo, c2hi, A.c2)) {
-                                if (m < kGEll) sh.list[m][i] = (uint16_t)j;
+                                if (m < kGEll) sh.list[m][i] = (uint16_t)(j | (sh.batch_of[j] == bi ? 0x8000 : 0));
                                 ++m;
                             }
                         }
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     };
                     if (!overflow) {
                         const int mc = sh.list_n[i];
-                        for (int t = 0; t < mc; ++t) visit_pair(sh.list[t][i]);
+                        for (int t = 0; t < mc; ++t) visit_pair(sh.list[t][i] & 0x7fff);
                     } else {
                         for_each_candidate(i, q, grid, sh.cell_start, sh.cell_circ, visit_pair);
                     }
@@ -367,8 +368,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                             if (act[c]) {
                                 const int i = ci[c];
                                 const float2 q = xt[c];
-                                auto term = [&](int j) {
-                                    const bool inb = sh.batch_of[j] == p;
+                                auto term_in = [&](int j, bool inb) {
                                     const float2 pj = inb ? sh.tpos[j] : sh.pos[j];
                                     const bool ce = inb ? j < i : true;    // Eq. 7
                                     pe += ce;
@@ -390,6 +390,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                                         pair_term32(q, pj, ce, two_r, four_r2, e, e1, gx, gy);
                                     }
                                 };
+                                auto term = [&](int j) { term_in(j, sh.batch_of[j] == p); };
                                 if (far) {
                                     // a circle of the batch left the skin: the other
                                     // circles from the cell grid, the batch's own from
@@ -403,7 +404,10 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                                     }
                                 } else if (!overflow) {
                                     const int mc = sh.list_n[i];
-                                    for (int t = 0; t < mc; ++t) term(sh.list[t][i]);
+                                    for (int t = 0; t < mc; ++t) {
+                                        const int en = sh.list[t][i];
+                                        term_in(en & 0x7fff, (en & 0x8000) != 0);
+                                    }
                                 } else {
                                     for_each_candidate(i, q, grid, sh.cell_start, sh.cell_circ, term);
                                 }
@@ -480,36 +484,39 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     float Bc[kNB];
 #pragma unroll
                     for (int a2 = 0; a2 < kNB; ++a2) Bc[a2] = lane < kNB ? Bwc[cur][a2 * kNB + lane] : 0.f;
-                    float dl = lane == kG ? 1.f : 0.f;
-                    float alph[kMM], rhoj[kMM];
+                    // two-loop on the Gram matrix: lane l keeps (B q)_l, the Gram
+                    // product of the current q with basis vector l (q = g at the
+                    // start), so each step is one readlane and one FMA
+                    const int jp = lane < kMM ? lane : lane - kMM;
+                    const bool live = lane < 2 * kMM && jp >= kMM - k;
+                    float rho_v = 0.f;              // 1 / s_j'y_j at lanes j and kMM + j
+                    if (live) rho_v = 1.f / Bwc[cur][(lane < kMM ? kMM + lane : lane - kMM) * kNB + lane];
+                    float acc = Bc[kG];
+                    float alph_v = 0.f;             // a_j at lanes j and kMM + j
 #pragma unroll
                     for (int j = kMM - 1; j >= 0; --j) {
-                        alph[j] = 0.f;
-                        rhoj[j] = 0.f;
-                        if (j >= kMM - k) {
-                            rhoj[j] = 1.f / lane_value(Bc[j], kMM + j);
-                            const float a = rhoj[j] * wave_sum_dpp(dl * Bc[j]);
-                            alph[j] = a;
-                            if (lane == kMM + j) dl -= a;
-                        }
+                        const float a = lane_value(rho_v * acc, j);           // rho_j s_j'q
+                        if (jp == j) alph_v = a;
+                        acc -= a * Bc[kMM + j];
                     }
-                    if (k > 0) dl *= lane_value(Bc[kMM - 1], 2 * kMM - 1) / lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
+                    float gam = 1.f;
+                    if (k > 0) gam = lane_value(Bc[kMM - 1], 2 * kMM - 1) / lane_value(Bc[2 * kMM - 1], 2 * kMM - 1);
+                    acc *= gam;
+                    float cs_v = 0.f;               // coefficient of s_j at lane j
 #pragma unroll
                     for (int j = 0; j < kMM; ++j) {
-                        if (j >= kMM - k) {
-                            const float bb = rhoj[j] * wave_sum_dpp(dl * Bc[kMM + j]);
-                            if (lane == j) dl += alph[j] - bb;
-                        }
+                        const float c = lane_value(alph_v - rho_v * acc, kMM + j);   // a_j - rho_j y_j'r
+                        if (lane == j) cs_v = c;
+                        acc += c * Bc[j];
                     }
-                    float gp = -wave_sum_dpp(dl * Bc[kG]);
+                    float gp = -lane_value(acc, kG);                               // g'p = -g'r
                     {
-                        const float cg = lane_value(dl, kG);
                         float cs[kMM], cy[kMM];
 #pragma unroll
-                        for (int j = 0; j < kMM; ++j) { cs[j] = lane_value(dl, j); cy[j] = lane_value(dl, kMM + j); }
+                        for (int j = 0; j < kMM; ++j) { cs[j] = lane_value(cs_v, j); cy[j] = -gam * lane_value(alph_v, j); }
 #pragma unroll
                         for (int c = 0; c < kGCPB; ++c) {
-                            float px = -cg * g[c].x, py = -cg * g[c].y;
+                            float px = -gam * g[c].x, py = -gam * g[c].y;
 #pragma unroll
                             for (int j = 0; j < kMM; ++j) {
                                 px -= cs[j] * S[j][c].x + cy[j] * Y[j][c].x;
@@ -609,6 +616,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     __syncthreads();
                     for (int i = tid; i < n; i += kGT) {
                         const float2 q = sh.pos[i];
+                        const int bi = sh.batch_of[i];
                         int m = 0;
                         const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
                         const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
@@ -619,7 +627,7 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                             for (int t = a; t < z; ++t) {
                                 const int j = sh.cell_circ[t];
                                 if (j != i && near_cut(q, sh.pos[j], c2lo, c2hi, A.c2)) {
-                                    if (m < kGEll) sh.list[m][i] = (uint16_t)j;
+                                    if (m < kGEll) sh.list[m][i] = (uint16_t)(j | (sh.batch_of[j] == bi ? 0x8000 : 0));
                                     ++m;
                                 }
                             }
