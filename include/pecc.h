@@ -323,11 +323,12 @@ int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t
  *     H_p <- (I - s y'/beta) H_p (I - y s'/beta) + s s'/beta,  beta = y's,
  * as H_p - (w s' + s w')/beta + (y'w/beta^2 + 1/beta) s s' with w = H_p y.
  * A direction with g'p >= 0 resets H_p to I.  FP32 matrices of 2|B_p|
- * rows of 2|B_p| floats, each row padded to a multiple of 4 floats, and
- * four vectors of 2|B_p| floats per batch live in the workspace (per
- * instance at most 4 * max_batch * max_n + 12 * max_n floats, max_batch >=
- * every batch's size; an instance whose batches need more reports
- * PECC_STATUS_BAD_INSTANCE).  The stored matrix runs one
+ * rows of 2|B_p| floats, each row padded to a multiple of 4 floats (64
+ * above 1024 floats), and four vectors of 2|B_p| floats per batch live in
+ * the workspace (per instance 4 * max_batch * max_n + 12 * max_n floats,
+ * + 132 * max_n when 2 * max_batch > 1024, rounded up to a multiple of 64;
+ * max_batch >= every batch's size; an instance whose batches need more
+ * reports PECC_STATUS_BAD_INSTANCE).  The stored matrix runs one
  * update behind (the newest update is carried as vectors and applied by
  * the next visit's pass), so a visit reads H_p once and writes it once: the
  * memory traffic per outer iteration falls as 1/k, which is where the

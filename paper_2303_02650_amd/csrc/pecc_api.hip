@@ -340,14 +340,17 @@ int pecc_gbo_kbatch_descend(const pecc_instances *inst, float *xy, const int32_t
 
 namespace {
 // floats of storage per instance for batches of at most max_batch circles:
-// the matrices, d_p = 2|B_p| rows of d_p rounded up to a multiple of 4
-// floats, sum_p d_p (d_p + 2) <= (2 max_batch + 2) sum_p d_p <= 4 max_batch
-// max_n + 4 max_n, and four vectors of d_p floats per batch (8 max_n); a
-// multiple of 4 floats, so every instance's region stays 16-byte aligned
+// the matrices, d_p = 2|B_p| rows of d_p floats rounded up to a multiple of
+// 4 (d_p <= 1024) or 64 (above), so sum_p d_p (d_p + pad) <= (2 max_batch
+// + pad) sum_p d_p <= 4 max_batch max_n + 2 pad max_n with pad = 2 or 62,
+// and four vectors of d_p floats per batch (8 max_n); rounded up to a
+// multiple of 64 floats, so every instance's region starts on a 256-byte
+// boundary like the workspace
 int64_t dense_stride(const pecc_instances *inst, int32_t max_batch)
 {
     const int64_t n = inst->max_n > 0 ? inst->max_n : 1;
-    return 4 * (int64_t)max_batch * n + 12 * n;
+    const int64_t pad = 2 * (int64_t)max_batch <= 1024 ? 2 : 62;
+    return (4 * (int64_t)max_batch * n + (2 * pad + 8) * n + 63) & ~(int64_t)63;
 }
 }  // namespace
 

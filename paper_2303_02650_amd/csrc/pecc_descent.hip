@@ -119,11 +119,11 @@ struct DenseShared {
 enum : int { kDnIdent = 1, kDnK = 2, kDnQ = 4, kDnSlot = 8 };
 
 // Work split of a pass over a symmetric d x d matrix (d even, d <= 2048)
-// stored row-major with rows of ld = d rounded up to a multiple of 4 floats
-// (16-byte aligned rows; the padding columns d, d + 1 of a d = 2 mod 4
-// matrix belong to no entry): an item is a column quad (four consecutive
-// columns, one 16-byte load per row, consecutive across a wave) and a
-// slice of the rows; there are at most BLOCK items, one per thread.
+// stored row-major with rows of sym_ld(d) floats (the padding columns from
+// d on belong to no entry; the quads cover d rounded up to 4 columns): an
+// item is a column quad (four consecutive columns, one 16-byte load per
+// row, consecutive across a wave) and a slice of the rows; there are at
+// most BLOCK items, one per thread.
 struct QuadSplit {
     int cq, nq, items;
     __device__ QuadSplit(int ld, int nthreads)
@@ -135,8 +135,15 @@ struct QuadSplit {
     }
 };
 
-// Row length of a dense batch matrix of order d.
-__device__ __forceinline__ int sym_ld(int d) { return (d + 3) & ~3; }
+// Row length of a dense batch matrix of order d (the largest order the
+// workspace bound allows for rows of d + 2 floats is 1024).  Up to 1024 a
+// multiple of 4 floats; above, a multiple of 64, so that rows start on
+// 256-byte boundaries (a wave's 1 KB of a row then spans 8 cache lines,
+// not 9: 6 % more matrix bandwidth at d = 2000 with every CU busy).
+// Smaller matrices are not padded further: a batch of them largely stays in
+// the last-level cache, where padding only adds footprint (measured slower
+// at d = 1000, 400 and 336).
+__device__ __forceinline__ int sym_ld(int d) { return d <= 1024 ? (d + 3) & ~3 : (d + 63) & ~63; }
 
 // One row of a thread's column quad: h holds S's four entries of the row
 // (I's when nothing is read), vq = (g, y, s, w) at the row, cs and cw s
@@ -173,7 +180,7 @@ __device__ __forceinline__ float4 quad_load(const float4 *col, int64_t st, int r
 }
 
 // One pass over a symmetric d x d matrix S (rows of sym_ld(d) floats,
-// 16-byte aligned): S g and S y as column sums (y_c = sum_r S[r][c] v[r] in
+// 16-byte aligned at least): S g and S y as column sums (y_c = sum_r S[r][c] v[r] in
 // ascending r per row slice, slices added in order: deterministic) into
 // part[k] = ((S g)_{2k}, (S g)_{2k+1}, (S y)_{2k}, (S y)_{2k+1}) for k <
 // d / 2, and with STORE S + U written back (U as in quad_elem, with ib and
@@ -187,8 +194,8 @@ __device__ void sym_pass(float *__restrict__ H, int d, const float4 *__restrict_
 {
     constexpr int U = 8;
     const int t = (int)threadIdx.x;
-    const int ld = sym_ld(d);
-    const QuadSplit sp(ld, BLOCK);
+    const int ld = sym_ld(d), dq = (d + 3) & ~3;
+    const QuadSplit sp(dq, BLOCK);
     const bool on = t < sp.items;
     const int qd = on ? t % sp.cq : 0, sl = on ? t / sp.cq : 0;
     const int q0 = on ? (int)((int64_t)d * sl / sp.nq) : 0;
@@ -231,7 +238,7 @@ __device__ void sym_pass(float *__restrict__ H, int d, const float4 *__restrict_
         quad_elem<STORE>(h, vr[q0 + r], cs, cw, ib, a2, acc);
         if constexpr (STORE) col[(int64_t)r * st] = h;
     }
-    const int cpl = ld / 2;
+    const int cpl = dq / 2;
     if (on) {
         part[sl * cpl + 2 * qd] = make_float4(acc[0], acc[1], acc[4], acc[5]);
         part[sl * cpl + 2 * qd + 1] = make_float4(acc[2], acc[3], acc[6], acc[7]);

@@ -286,15 +286,17 @@ def test_dense_descents_reach_oracle_outcomes(P):
 
 
 def test_dense_workspace_bound(P):
-    # per instance 4 max_batch max_n + 12 max_n floats; two batches of 10
-    # circles (d = 20, rows of 20 floats) need 2 (20 * 20 + 4 * 20) = 960,
-    # which max_batch = 9 gives exactly and max_batch = 8 (880) does not
-    inst = synth.C1()
+    # per instance 4 max_batch max_n + 12 max_n floats (2 max_batch <= 1024),
+    # rounded up to a multiple of 64; rows of d = 2|B_p| floats padded to a
+    # multiple of 4.  Two batches of 100 circles (d = 200) need
+    # 2 (200 * 200 + 4 * 200) = 81600 floats: max_batch = 98 gives 80832
+    # (80800 rounded up), too little; 99 gives 81600 and 100 more
+    inst = synth.instance_set(1, 200, float(np.sqrt(200 / 0.84)), seed=7)
     bo = host_partition(inst, "sector", 2)
-    assert sorted(np.bincount(bo, minlength=2).tolist()) == [10, 10]
-    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=8)
+    assert sorted(np.bincount(bo, minlength=2).tolist()) == [100, 100]
+    _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=98)
     assert P.STATUS[res["status"][0]] == "BAD_INSTANCE"
-    for mb in (9, 10):
+    for mb in (99, 100):
         _, res = run_dense(P, inst, bo, 2, P.DescentParams(max_iter=3), max_batch=mb)
         assert P.STATUS[res["status"][0]] != "BAD_INSTANCE"
 
