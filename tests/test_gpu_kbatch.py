@@ -265,6 +265,32 @@ def test_dense_first_outer_iterations_follow_oracle(P, name, outer):
         assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-3)
 
 
+@pytest.mark.parametrize("outer", [4, 8])
+def test_dense_large_matrices_follow_oracle(P, outer):
+    """One batch of 995 and of 887 circles (C3 restarts): matrices of 1990
+    and 1774 rows, stored in rows of 2048 and 1792 floats (the layout above
+    1024 rows), read and written from the fourth visit on.  From these
+    near-converged starts the steps stay short and the FP32 descent follows
+    the FP64 oracle closely (from random starts at this size a line-search
+    halving decided differently in FP32 and FP64 separates the trajectories
+    after the second update)."""
+    full = synth.C3_restarts()
+    inst = synth.pack([full.instance(i) for i in (12, 0)], [full.R[i] for i in (12, 0)])
+    assert list(np.diff(inst.offset)) == [995, 887]
+    bo = host_partition(inst, "sector", 1)
+    xg, res = run_dense(P, inst, bo, 1, P.DescentParams(max_iter=outer, g_tol=0.0, ftol=0.0))
+    for b in range(inst.B):
+        o0, o1 = inst.offset[b], inst.offset[b + 1]
+        x64, r64, _ = oracle.gbo_seq_descend(inst.instance(b).astype(np.float64), inst.R[b],
+                                             bo[o0:o1], 1, oracle.DescentParams(g_tol=0.0),
+                                             max_outer=outer, dense=True)
+        assert res["iters"][b] == r64["outer"] == outer
+        scale = max(1.0, float(np.abs(x64).max()))
+        err = np.abs(xg[o0:o1] - x64).max() / scale
+        assert err < 2e-5, (b, err)
+        assert res["gnorm"][b] == pytest.approx(r64["gsum"], rel=1e-4)
+
+
 def test_dense_descents_reach_oracle_outcomes(P):
     inst = synth.instance_set(16, 20, 5.2, seed=9)            # C1-shaped starts
     for k in (1, 2):
