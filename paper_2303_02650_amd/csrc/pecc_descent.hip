@@ -309,6 +309,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     constexpr bool SEQ = MODE == kModeSeq || DENSE;
     // whole instance: one wave takes the uniform decisions of an evaluation
     constexpr bool SOLO = MODE == kModeWhole || MODE == kModeSeq;
+    // every wave decides in the other modes; among them the batch mode is the dense one
+    static_assert(SOLO || !SEQ || DENSE, "a limited-memory batch mode decides on one wave");
     constexpr int ELL = SEQ ? kEllSeq : kEll;
     __shared__ DescentShared<ELL> sh;
     __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
@@ -489,19 +491,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         };
         // batch descent: batch bb's saved Gram matrix into B (every wave
         // writes the same values and reads back its own)
-        auto load_gram = [&](int bb) {
-            if constexpr (SEQ && !DENSE) {
-                const int ln = (int)threadIdx.x & (kWave - 1);
-#pragma unroll
-                for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
-                    const int ent = ln + kWave * r;
-                    if (ent < kNB * kNB) sh.Bm[cur][ent] = sq.BmP[bb][ent];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-        };
         // ANM (Alg. 3), one call: cnt += 1; once cnt >= len the neighbor
         // lists of the current positions are compared with the stored ones
         // (same predicate; as sets).  Different (or the stored lists did not
@@ -1603,9 +1592,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     nvis = 0;
                     nstall = 0;
                     cb = first_b;
-                    // the batch's saved Gram matrix; no wave reads B before
-                    // the next evaluation's barriers
-                    load_gram(cb);
                     k = __builtin_amdgcn_readlane(kb_v, cb);
                     req = kReqInit;
                     continue;
@@ -1680,20 +1666,10 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 
             if constexpr (SEQ) {
                 if (visits && vend) {
-                    // ---- end of a visit: save the batch's Gram matrix (every
-                    // wave has finished with B), then the next batch
+                    // ---- end of a visit (this path's batch mode is the dense
+                    // one): record the accepted pair, then the next batch
                     kb_v = lane == cb ? k : kb_v;
-                    if constexpr (DENSE) {
-                        if (push) dense_record(lane_value(tot, sScYc), sc, yc);
-                    } else {
-                        __syncthreads();
-#pragma unroll
-                        for (int r = 0; r < (kNB * kNB + kWave - 1) / kWave; ++r) {
-                            const int ent = lane + kWave * r;
-                            if (ent < kNB * kNB) sq.BmP[cb][ent] = sh.Bm[cur][ent];
-                        }
-                        __syncthreads();
-                    }
+                    if (push) dense_record(lane_value(tot, sScYc), sc, yc);
                     int nx = cb + 1;
                     while (nx < A.nbat && sq.cnt[nx] == 0) ++nx;
                     if (nx >= A.nbat) {           // outer iteration done
@@ -1704,7 +1680,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         continue;
                     }
                     cb = nx;
-                    load_gram(cb);
                     k = __builtin_amdgcn_readlane(kb_v, cb);
                     req = kReqInit;
                     continue;
