@@ -89,6 +89,7 @@ struct DescentShared {
         float c1, eps_curv, ftol, g_tol_sq, g_tol;
         int m, max_halvings, max_iter, nbat, anm;
     } dk;
+    float dec_Rz, dec_pR;          // container adjustment: radius and its search component
 };
 
 // Batch descent only: the saved Gram matrix of every batch, batch ids and
@@ -270,11 +271,13 @@ enum : int { kDecAccept = 1, kDecPush = 2, kDecStop = 4, kDecNext = 8, kDecSteep
 // ADJ: container adjustment (Sec. 4.2, Eq. 12, Alg. 2).  The radius joins
 // the variables, the objective is U = E + lambda R^2 and A.rounds
 // minimisations run with lambda halved after each (a fresh history every
-// round).  Lane l additionally holds the radius component of basis vector l
-// (hR_v), so after the fused reduction every Gram entry gets its R x R
-// product added, and the unit-circle energy slot carries sum_i d_i0 instead,
-// from which dU/dR = -2 sum_i d_i0 + 2 lambda R.  FP32 throughout (no FP64
-// regime, no FEASIBLE stop: U > 0); Rout[b] receives the final radius.
+// round).  The deciding wave additionally holds in lane l the radius
+// component of basis vector l (hR_v), so after the fused reduction every
+// Gram entry gets its R x R product added, and the unit-circle energy slot
+// carries sum_i d_i0 instead, from which dU/dR = -2 sum_i d_i0 + 2 lambda R;
+// the radius and its search component reach the other waves with the
+// decision.  FP32 throughout (no FP64 regime, no FEASIBLE stop: U > 0);
+// Rout[b] receives the final radius.
 //
 // SEQ: batch descent of Alg. 1 over the partition part[] into A.nbat
 // batches.  An outer iteration visits the non-empty batches in index order;
@@ -308,9 +311,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
     constexpr bool DENSE = MODE == kModeDense;
     constexpr bool SEQ = MODE == kModeSeq || DENSE;
     // whole instance: one wave takes the uniform decisions of an evaluation
-    constexpr bool SOLO = MODE == kModeWhole || MODE == kModeSeq;
-    // every wave decides in the other modes; among them the batch mode is the dense one
-    static_assert(SOLO || !SEQ || DENSE, "a limited-memory batch mode decides on one wave");
+    constexpr bool SOLO = MODE == kModeWhole || MODE == kModeSeq || MODE == kModeAdj;
+    // every wave decides only in the dense mode
+    static_assert(SOLO || DENSE, "the limited-memory modes decide on one wave");
     constexpr int ELL = SEQ ? kEllSeq : kEll;
     __shared__ DescentShared<ELL> sh;
     __shared__ std::conditional_t<DENSE, DenseShared, std::conditional_t<SEQ, SeqShared, NoShared>> sq;
@@ -911,8 +914,8 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
         }
 
         // container adjustment state (uniform): radius, its gradient and
-        // search components, penalty coefficient; hR_v: radius component of
-        // basis vector `lane`
+        // search components, penalty coefficient; hR_v (deciding wave):
+        // radius component of basis vector `lane`
         float Rz = R, gR = 0.f, pR = 0.f, lam = ADJ ? A.lambda0 : 0.f;
         float hR_v = 0.f;
         int iters_all = 0;
@@ -923,8 +926,9 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             // the previous round's reads of B before it is cleared
             __syncthreads();
             for (int q = tid; q < kNB * kNB; q += kDB) { sh.Bm[0][q] = 0.f; sh.Bm[1][q] = 0.f; }
+            for (int q = tid; q < kNB * kRS; q += kDB) sh.Bring[q] = 0.f;
             for (int q = tid; q < 2 * kMM; q += kDB) sh.rho[q / kMM][q % kMM] = 0.f;
-            k = 0; cur = 0; it = 0; h = 0; status = 0;
+            k = 0; cur = 0; it = 0; itw = 0; hd = 0; h = 0; status = 0;
             req = kReqInit;
             hR_v = 0.f;
         }
@@ -1256,6 +1260,37 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         so = lane_value64(vo, 0);
                         st = lane_value64(vt, 0);
                     }
+                    // container adjustment: the radius components of the reduced
+                    // dot products (lane L holds slot L, whose operands are
+                    // (trial gradient | step | change of gradient) and (a basis
+                    // vector | one of those three)); hR_v: the radius component
+                    // of basis vector `lane`, kept by this wave
+                    float gRt = 0.f, scR = 0.f, ycR = 0.f;
+                    if constexpr (ADJ) {
+                        gRt = -2.f * lane_value(tot, sE1) + 2.f * lam * Rt;   // dU/dR at the trial
+                        scR = Rt - Rz;
+                        ycR = gRt - gR;
+                        const int L = lane;
+                        int bsel = 0;
+                        float uR = 0.f;
+                        if (L < 2 * kMM) { bsel = L; uR = gRt; }                                   // gt . s_j, gt . y_j
+                        else if (L < 3 * kMM - 1) { bsel = L - 2 * kMM + 1; uR = scR; }            // sc . s_j
+                        else if (L < 4 * kMM - 2) { bsel = kMM + L - (3 * kMM - 1) + 1; uR = scR; } // sc . y_j
+                        else if (L < 5 * kMM - 3) { bsel = L - (4 * kMM - 2) + 1; uR = ycR; }      // yc . s_j
+                        else if (L < 6 * kMM - 4) { bsel = kMM + L - (5 * kMM - 3) + 1; uR = ycR; } // yc . y_j
+                        const float vR = __builtin_bit_cast(
+                            float, __builtin_amdgcn_ds_bpermute(4 * bsel, __builtin_bit_cast(int, hR_v)));
+                        float corr = uR * vR;
+                        if (L == sGG) corr = gRt * gRt;
+                        else if (L == sScSc) corr = scR * scR;
+                        else if (L == sScYc) corr = scR * ycR;
+                        else if (L == sYcYc) corr = ycR * ycR;
+                        else if (L == sScG) corr = scR * gRt;
+                        else if (L == sYcG) corr = ycR * gRt;
+                        else if (L == sE) corr = lam * Rt * Rt;               // U = E + lambda R^2
+                        else if (L == sE1) corr = 0.f;
+                        tot += corr;
+                    }
                     const float Et = lane_value(tot, sE);
                     const float E1t = lane_value(tot, sE1);
                     // batch descent: more than one batch, visited in turn
@@ -1357,14 +1392,28 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                 }
                                 if (!SEQ && lane == 0) sh.rho[0][hd_old] = 1.f / lane_value(tot, sScYc);
                             }
+                            if constexpr (ADJ) {
+                                if (push) {             // shift the radius components like S and Y
+                                    const int L = lane;
+                                    const int src = (L < kMM - 1 || (L >= kMM && L < 2 * kMM - 1)) ? L + 1 : L;
+                                    float v = __builtin_bit_cast(
+                                        float, __builtin_amdgcn_ds_bpermute(4 * src, __builtin_bit_cast(int, hR_v)));
+                                    if (L == kMM - 1) v = scR;
+                                    if (L == 2 * kMM - 1) v = ycR;
+                                    hR_v = v;
+                                }
+                                Rz = Rt;
+                                gR = gRt;
+                            }
                             if (req == kReqTrial && !vis) {
                                 ++it;
                                 itw = itw == W ? 0 : itw + 1;
                             }
                             E = Et;
                             if (fp64) { E64o = so; E64t = st; }
-                            // FP64 regime once either FP32 energy is small
-                            if (!vis && !fp64 && tau64 > 0.0 && (double)fminf(E, E1t) < tau64) {
+                            // FP64 regime once either FP32 energy is small (not
+                            // when adjusting: U > 0 and no FEASIBLE stop)
+                            if (!ADJ && !vis && !fp64 && tau64 > 0.0 && (double)fminf(E, E1t) < tau64) {
                                 fp64 = true;
                                 req = kReqFp64;          // FP64 energies of x before going on
                                 fl |= kDecNext;
@@ -1457,10 +1506,21 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                                 fl |= kDecStop;
                             } else {
                                 gp = gpv;
+                                if constexpr (ADJ) {
+                                    // radius component of the direction
+                                    const float cy_v = -gam * alph_v;
+                                    float pr = -gam * gR;
+#pragma unroll
+                                    for (int j = 0; j < kMM; ++j)
+                                        pr -= lane_value(cs_v, j) * lane_value(hR_v, j) +
+                                              lane_value(cy_v, j) * lane_value(hR_v, kMM + j);
+                                    pR = pr;
+                                }
                                 if (k > 0 && !(gp < 0.f)) {
                                     k = 0;
                                     gp = -gg;
                                     fl |= kDecSteepest;
+                                    if constexpr (ADJ) pR = -gR;
                                 }
                                 if (k > 0) alpha = 1.f;
                                 else alpha = 1.f / fmaxf(1.f, sqrtf(gg0));
@@ -1480,6 +1540,7 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         sh.dec_fp64 = fp64 ? 1 : 0;
                         sh.dec_alpha = alpha;
                         sh.dec_cb = cb;
+                        if constexpr (ADJ) { sh.dec_Rz = Rz; sh.dec_pR = pR; }
                     }
                 }
                 __syncthreads();                                        // B3
@@ -1489,6 +1550,10 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 alpha = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                                       __builtin_bit_cast(int, sh.dec_alpha)));
                 if constexpr (SEQ) cb = __builtin_amdgcn_readfirstlane(sh.dec_cb);
+                if constexpr (ADJ) {
+                    Rz = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, sh.dec_Rz)));
+                    pR = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, sh.dec_pR)));
+                }
                 if (fl & kDecAccept) {
                     const bool push = (fl & kDecPush) != 0;
 #pragma unroll
@@ -1539,35 +1604,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
             if (want64) {
 #pragma unroll
                 for (int w = 0; w < kDW; ++w) { so += sh.red64[par][w][0]; st += sh.red64[par][w][1]; }
-            }
-            float gRt = 0.f, scR = 0.f, ycR = 0.f;
-            if constexpr (ADJ) {
-                // radius components of the reduced dot products: lane L holds
-                // slot L, whose operands are (trial gradient | step | change of
-                // gradient) and (a basis vector | one of those three)
-                gRt = -2.f * lane_value(tot, sE1) + 2.f * lam * Rt;     // dU/dR at the trial
-                scR = Rt - Rz;
-                ycR = gRt - gR;
-                const int L = lane;
-                int bsel = 0;
-                float uR = 0.f;
-                if (L < 2 * kMM) { bsel = L; uR = gRt; }                                   // gt . s_j, gt . y_j
-                else if (L < 3 * kMM - 1) { bsel = L - 2 * kMM + 1; uR = scR; }            // sc . s_j
-                else if (L < 4 * kMM - 2) { bsel = kMM + L - (3 * kMM - 1) + 1; uR = scR; } // sc . y_j
-                else if (L < 5 * kMM - 3) { bsel = L - (4 * kMM - 2) + 1; uR = ycR; }      // yc . s_j
-                else if (L < 6 * kMM - 4) { bsel = kMM + L - (5 * kMM - 3) + 1; uR = ycR; } // yc . y_j
-                const float vR = __builtin_bit_cast(
-                    float, __builtin_amdgcn_ds_bpermute(4 * bsel, __builtin_bit_cast(int, hR_v)));
-                float corr = uR * vR;
-                if (L == sGG) corr = gRt * gRt;
-                else if (L == sScSc) corr = scR * scR;
-                else if (L == sScYc) corr = scR * ycR;
-                else if (L == sYcYc) corr = ycR * ycR;
-                else if (L == sScG) corr = scR * gRt;
-                else if (L == sYcG) corr = ycR * gRt;
-                else if (L == sE) corr = lam * Rt * Rt;                 // U = E + lambda R^2
-                else if (L == sE1) corr = 0.f;
-                tot += corr;
             }
             const float Et = lane_value(tot, sE);
             const float E1t = lane_value(tot, sE1);
@@ -1637,26 +1673,13 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                     g[c] = gt[c];
                 }
                 if (push) k = k + 1 > A.m ? A.m : k + 1;
-                if constexpr (ADJ) {
-                    if (push) {                 // shift the radius components like S and Y
-                        const int L = lane;
-                        const int src = (L < kMM - 1 || (L >= kMM && L < 2 * kMM - 1)) ? L + 1 : L;
-                        float v = __builtin_bit_cast(
-                            float, __builtin_amdgcn_ds_bpermute(4 * src, __builtin_bit_cast(int, hR_v)));
-                        if (L == kMM - 1) v = scR;
-                        if (L == 2 * kMM - 1) v = ycR;
-                        hR_v = v;
-                    }
-                    Rz = Rt;
-                    gR = gRt;
-                }
                 if (req == kReqTrial && !(SEQ && visits)) ++it;   // visits: outer iterations
                 E = Et;
                 if (fp64) { E64o = so; E64t = st; }
                 // FP64 regime once either FP32 energy is small: with a contact
                 // margin the unit circles can be overlap-free while E (radius
                 // rad) still sums (2 mu)^2 over every contact
-                if (!ADJ && !(SEQ && visits) && !fp64 && A.tau64 > 0.0 &&
+                if (!(SEQ && visits) && !fp64 && A.tau64 > 0.0 &&
                     (double)fminf(E, E1t) < A.tau64) {
                     fp64 = true;
                     req = kReqFp64;          // FP64 energies of x before going on
@@ -1730,14 +1753,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(px, py)
                                                                   : make_float2(0.f, 0.f);
                     }
-                    if constexpr (ADJ) {
-                        float pr = -gam * gR;
-    #pragma unroll
-                        for (int j = 0; j < kMM; ++j)
-                            pr -= lane_value(cs_v, j) * lane_value(hR_v, j) +
-                                  lane_value(cy_v, j) * lane_value(hR_v, kMM + j);
-                        pR = pr;
-                    }
                 }
             }
             if (k > 0 && !(gp < 0.f)) {
@@ -1747,7 +1762,6 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                 for (int c = 0; c < kCPT; ++c)
                     p[c] = (!SEQ || !visits || batc_of(c) == cb) ? make_float2(-g[c].x, -g[c].y)
                                                               : make_float2(0.f, 0.f);
-                if constexpr (ADJ) pR = -gR;
                 gp = -gg;
             }
             if (k > 0) alpha = 1.f;
