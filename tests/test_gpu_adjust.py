@@ -54,14 +54,17 @@ def test_proven_optima(P, name, xy, R0, Ropt):
     assert abs(Ro - Ropt) < 1e-8
 
 
-def test_first_iterations_follow_the_oracle(P):
+@pytest.mark.parametrize("margin", [0.0, 1e-4])
+def test_first_iterations_follow_the_oracle(P, margin):
+    """With a contact margin mu the GPU's circles have radius 1 + mu, in the
+    pair and the containment terms alike: the oracle's radius."""
     rng = np.random.default_rng(3)
     xy = synth.disk_uniform(30, 6.5, rng)
     inst = synth.pack([xy], [6.5])
     for iters in (1, 2, 4):
-        prm = P.DescentParams(max_iter=iters, g_tol=0.0, ftol=0.0, contact_margin=0.0)
+        prm = P.DescentParams(max_iter=iters, g_tol=0.0, ftol=0.0, contact_margin=margin)
         x, R, res, d, xyd = run(P, inst, prm, rounds=1)
-        po = oracle.DescentParams(max_iter=iters, g_tol=0.0, ftol=0.0)
+        po = oracle.DescentParams(max_iter=iters, g_tol=0.0, ftol=0.0, rad=1.0 + margin)
         xo, Ro, ro = oracle.adjust_container(inst.xy.astype(np.float64), 6.5, po, 1e-4, 1)
         assert res["iters"][0] == ro["iters"] == iters
         assert abs(R[0] - Ro) <= 1e-5 * max(1.0, abs(Ro)), (iters, R[0], Ro)
