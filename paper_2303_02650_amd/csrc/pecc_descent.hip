@@ -996,23 +996,56 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
 #pragma unroll
                 for (int c = 0; c < kCPT; ++c) {
                     const int i = tid + c * kDB;
-                    if (act[c]) {
-                        int m = 0, up = 0;
+                    // the candidates are the circles of the 3 x 3 cells
+                    // around the circle's own, in cell order: three cell rows
+                    // (start, length), read together, indexed as one run
+                    int ra[3], rl[3];
+                    {
                         const int cx = cell_coord(xt[c].x, grid), cy = cell_coord(xt[c].y, grid);
                         const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
                         const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
-                        for (int yy = y0; yy <= y1; ++yy) {
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            const bool row = act[c] && y0 + r <= y1;
+                            const int yy = y0 + r <= y1 ? y0 + r : y0;
                             const int a = sh.cell_start[yy * grid.nc + x0];
                             const int z = sh.cell_start[yy * grid.nc + x1 + 1];
-                            for (int t = a; t < z; ++t) {
-                                const int j = sh.cell_circ[t];
-                                if (j != i && near_cut(xt[c], sh.pos[j], c2lo, c2hi, A.c2)) {
-                                    if (m < ELL) sh.list[m][i] = (uint16_t)(j * (int)sizeof(float2));
-                                    ++m;
-                                    up += j > i;
-                                }
+                            ra[r] = row ? a : 0;
+                            rl[r] = row ? z - a : 0;
+                        }
+                    }
+                    const int K = rl[0] + rl[1] + rl[2];
+                    // the wave walks its longest run, four candidates per
+                    // step with their index and position reads in flight
+                    const int kmax = wave_max_dpp(K);
+                    int m = 0, up = 0;
+                    for (int k0 = 0; k0 < kmax; k0 += 4) {
+                        int jv[4];
+                        bool ok[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int k = k0 + u;
+                            ok[u] = k < K;
+                            const int t = k < rl[0]         ? ra[0] + k
+                                        : k < rl[0] + rl[1] ? ra[1] + (k - rl[0])
+                                                            : ra[2] + (k - rl[0] - rl[1]);
+                            const int jj = sh.cell_circ[ok[u] ? t : 0];
+                            jv[u] = ok[u] ? jj : i;
+                        }
+                        float2 pv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) pv[u] = sh.pos[jv[u]];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = jv[u];
+                            if (ok[u] && j != i && near_cut(xt[c], pv[u], c2lo, c2hi, A.c2)) {
+                                if (m < ELL) sh.list[m][i] = (uint16_t)(j * (int)sizeof(float2));
+                                ++m;
+                                up += j > i;
                             }
                         }
+                    }
+                    if (act[c]) {
                         if (m > ELL) sh.over = 1;
                         sh.list_n[i] = (uint8_t)(m < ELL ? m : ELL);
                         up_c[c] = up;
