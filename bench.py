@@ -41,13 +41,13 @@ COPY_BYTES = 1 << 30             # calibration copy: 1 GiB read + 1 GiB written
 SWEEP_TRAFFIC_BYTES_65536 = 1.9769e9
 # HBM bytes per launch of lbfgs_descend_kernel for the 256-instance main step
 # (same counter runs): profiles/lbfgs_descend_kernel_traffic_256x1000.md.
-DESCENT_TRAFFIC_BYTES_256 = 4.67e6
+DESCENT_TRAFFIC_BYTES_256 = 4.77e6
 # Instruction counters of the same launch (SQ_INSTS_VALU per wave per
 # evaluation, SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES):
 # profiles/lbfgs_descend_kernel_sq_counters_256x1000.md.  Valid for the
 # kernel as profiled.
-DESCENT_VALU_PER_WAVE_EVAL_256 = 1159
-DESCENT_VALU_ACTIVE_SHARE_256 = 0.321
+DESCENT_VALU_PER_WAVE_EVAL_256 = 1164
+DESCENT_VALU_ACTIVE_SHARE_256 = 0.332
 
 N_CIRCLES, R_C2, BATCH = 1000, 34.6, 256
 

@@ -1035,14 +1035,29 @@ __global__ __launch_bounds__(kDB) void lbfgs_descend_kernel(
                         float2 pv[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) pv[u] = sh.pos[jv[u]];
+                        // the FP32 test decides outside a band of +-1e-5
+                        // around the cutoff, the FP64 one inside it (the
+                        // near_cut predicate; the band is rare, so one uniform
+                        // branch covers the wave's four candidates)
+                        bool nb[4], band[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int j = jv[u];
-                            if (ok[u] && j != i && near_cut(xt[c], pv[u], c2lo, c2hi, A.c2)) {
-                                if (m < ELL) sh.list[m][i] = (uint16_t)(j * (int)sizeof(float2));
-                                ++m;
-                                up += j > i;
-                            }
+                            const float dx = xt[c].x - pv[u].x, dy = xt[c].y - pv[u].y;
+                            const float l2 = dx * dx + dy * dy;
+                            const bool cand = ok[u] && jv[u] != i;
+                            nb[u] = cand && l2 < c2lo;
+                            band[u] = cand && l2 >= c2lo && l2 <= c2hi;
+                        }
+                        if (__builtin_amdgcn_ballot_w64(band[0] || band[1] || band[2] || band[3])) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (band[u]) nb[u] = near64(xt[c], pv[u], A.c2);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (nb[u] && m < ELL) sh.list[m][i] = (uint16_t)(jv[u] * (int)sizeof(float2));
+                            m += nb[u] ? 1 : 0;
+                            up += (nb[u] && jv[u] > i) ? 1 : 0;
                         }
                     }
                     if (act[c]) {
