@@ -202,27 +202,79 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                 }
                 if (tid == 0) sh.over = 0;
                 __syncthreads();
-                for (int i = tid; i < n; i += kGT) {
-                    const float2 q = sh.pos[i];
-                    const int bi = sh.batch_of[i];
-                    int m = 0;
-                    const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
-                    const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
-                    const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
-                    for (int yy = y0; yy <= y1; ++yy) {
-                        const int a = sh.cell_start[yy * grid.nc + x0];
-                        const int z = sh.cell_start[yy * grid.nc + x1 + 1];
-                        for (int t = a; t < z; ++t) {
-                            const int j = sh.cell_circ[t];
-                            if (j != i && near_cut(q, sh.pos[j], c2lo, c2hi, A.c2)) {
-                                if (m < kGEll) sh.list[m][i] = (uint16_t)(j | (sh.batch_of[j] == bi ? 0x8000 : 0));
-                                ++m;
-                            }
+                for (int i0 = 0; i0 < n; i0 += kGT) {
+                    const int i = i0 + tid;
+                    const bool act = i < n;
+                    const float2 q = sh.pos[act ? i : 0];
+                    const int bi = sh.batch_of[act ? i : 0];
+                    // candidates: the circles of the 3 x 3 cells around q's, in cell
+                    // order; three cell rows (start, length), read together, one run
+                    int ra[3], rl[3];
+                    {
+                        const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
+                        const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
+                        const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) {
+                            const bool row = act && y0 + r <= y1;
+                            const int yy = y0 + r <= y1 ? y0 + r : y0;
+                            const int a = sh.cell_start[yy * grid.nc + x0];
+                            const int z = sh.cell_start[yy * grid.nc + x1 + 1];
+                            ra[r] = row ? a : 0;
+                            rl[r] = row ? z - a : 0;
                         }
                     }
-                    if (m > kGEll) sh.over = 1;
-                    sh.list_n[i] = (uint8_t)(m < kGEll ? m : kGEll);
-                    sh.xref[i] = q;
+                    const int K = rl[0] + rl[1] + rl[2];
+                    // the wave walks its longest run, four candidates per step with their
+                    // reads in flight; FP32 test outside the +-1e-5 band around the
+                    // cutoff, FP64 inside (near_cut), behind one uniform branch
+                    const int kmax = wave_max_dpp(K);
+                    int m = 0;
+                    for (int k0 = 0; k0 < kmax; k0 += 4) {
+                        int jv[4];
+                        bool ok[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int k = k0 + u;
+                            ok[u] = k < K;
+                            const int t = k < rl[0]         ? ra[0] + k
+                                        : k < rl[0] + rl[1] ? ra[1] + (k - rl[0])
+                                                            : ra[2] + (k - rl[0] - rl[1]);
+                            const int jj = sh.cell_circ[ok[u] ? t : 0];
+                            jv[u] = ok[u] ? jj : 0;
+                        }
+                        float2 pv[4];
+                        int bj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            pv[u] = sh.pos[jv[u]];
+                            bj[u] = sh.batch_of[jv[u]];
+                        }
+                        bool nb[4], band[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float dx = q.x - pv[u].x, dy = q.y - pv[u].y;
+                            const float l2 = dx * dx + dy * dy;
+                            const bool cand = ok[u] && jv[u] != i;
+                            nb[u] = cand && l2 < c2lo;
+                            band[u] = cand && l2 >= c2lo && l2 <= c2hi;
+                        }
+                        if (__builtin_amdgcn_ballot_w64(band[0] || band[1] || band[2] || band[3])) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (band[u]) nb[u] = near64(q, pv[u], A.c2);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (nb[u] && m < kGEll) sh.list[m][i] = (uint16_t)(jv[u] | (bj[u] == bi ? 0x8000 : 0));
+                            m += nb[u] ? 1 : 0;
+                        }
+                    }
+                    if (act) {
+                        if (m > kGEll) sh.over = 1;
+                        sh.list_n[i] = (uint8_t)(m < kGEll ? m : kGEll);
+                        sh.xref[i] = q;
+                    }
                 }
                 ++rebuilds;
                 if (tid == 0) sh.flag = 0;
@@ -614,27 +666,79 @@ __global__ __launch_bounds__(kGT) void gbo_descend_kernel(
                     }
                     if (tid == 0) sh.over = 0;
                     __syncthreads();
-                    for (int i = tid; i < n; i += kGT) {
-                        const float2 q = sh.pos[i];
-                        const int bi = sh.batch_of[i];
-                        int m = 0;
-                        const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
-                        const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
-                        const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
-                        for (int yy = y0; yy <= y1; ++yy) {
-                            const int a = sh.cell_start[yy * grid.nc + x0];
-                            const int z = sh.cell_start[yy * grid.nc + x1 + 1];
-                            for (int t = a; t < z; ++t) {
-                                const int j = sh.cell_circ[t];
-                                if (j != i && near_cut(q, sh.pos[j], c2lo, c2hi, A.c2)) {
-                                    if (m < kGEll) sh.list[m][i] = (uint16_t)(j | (sh.batch_of[j] == bi ? 0x8000 : 0));
-                                    ++m;
-                                }
+                    for (int i0 = 0; i0 < n; i0 += kGT) {
+                        const int i = i0 + tid;
+                        const bool act = i < n;
+                        const float2 q = sh.pos[act ? i : 0];
+                        const int bi = sh.batch_of[act ? i : 0];
+                        // candidates: the circles of the 3 x 3 cells around q's, in cell
+                        // order; three cell rows (start, length), read together, one run
+                        int ra[3], rl[3];
+                        {
+                            const int cx = cell_coord(q.x, grid), cy = cell_coord(q.y, grid);
+                            const int y0 = cy > 0 ? cy - 1 : 0, y1 = cy < grid.nc - 1 ? cy + 1 : grid.nc - 1;
+                            const int x0 = cx > 0 ? cx - 1 : 0, x1 = cx < grid.nc - 1 ? cx + 1 : grid.nc - 1;
+#pragma unroll
+                            for (int r = 0; r < 3; ++r) {
+                                const bool row = act && y0 + r <= y1;
+                                const int yy = y0 + r <= y1 ? y0 + r : y0;
+                                const int a = sh.cell_start[yy * grid.nc + x0];
+                                const int z = sh.cell_start[yy * grid.nc + x1 + 1];
+                                ra[r] = row ? a : 0;
+                                rl[r] = row ? z - a : 0;
                             }
                         }
-                        if (m > kGEll) sh.over = 1;
-                        sh.list_n[i] = (uint8_t)(m < kGEll ? m : kGEll);
-                        sh.xref[i] = q;
+                        const int K = rl[0] + rl[1] + rl[2];
+                        // the wave walks its longest run, four candidates per step with their
+                        // reads in flight; FP32 test outside the +-1e-5 band around the
+                        // cutoff, FP64 inside (near_cut), behind one uniform branch
+                        const int kmax = wave_max_dpp(K);
+                        int m = 0;
+                        for (int k0 = 0; k0 < kmax; k0 += 4) {
+                            int jv[4];
+                            bool ok[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int k = k0 + u;
+                                ok[u] = k < K;
+                                const int t = k < rl[0]         ? ra[0] + k
+                                            : k < rl[0] + rl[1] ? ra[1] + (k - rl[0])
+                                                                : ra[2] + (k - rl[0] - rl[1]);
+                                const int jj = sh.cell_circ[ok[u] ? t : 0];
+                                jv[u] = ok[u] ? jj : 0;
+                            }
+                            float2 pv[4];
+                            int bj[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                pv[u] = sh.pos[jv[u]];
+                                bj[u] = sh.batch_of[jv[u]];
+                            }
+                            bool nb[4], band[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const float dx = q.x - pv[u].x, dy = q.y - pv[u].y;
+                                const float l2 = dx * dx + dy * dy;
+                                const bool cand = ok[u] && jv[u] != i;
+                                nb[u] = cand && l2 < c2lo;
+                                band[u] = cand && l2 >= c2lo && l2 <= c2hi;
+                            }
+                            if (__builtin_amdgcn_ballot_w64(band[0] || band[1] || band[2] || band[3])) {
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (band[u]) nb[u] = near64(q, pv[u], A.c2);
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (nb[u] && m < kGEll) sh.list[m][i] = (uint16_t)(jv[u] | (bj[u] == bi ? 0x8000 : 0));
+                                m += nb[u] ? 1 : 0;
+                            }
+                        }
+                        if (act) {
+                            if (m > kGEll) sh.over = 1;
+                            sh.list_n[i] = (uint8_t)(m < kGEll ? m : kGEll);
+                            sh.xref[i] = q;
+                        }
                     }
                     ++rebuilds;
                     if (tid == 0) sh.flag = 0;
